@@ -1,0 +1,111 @@
+"""Whole-field numpy twin of the C oracle (TEST INFRASTRUCTURE ONLY).
+
+Written independently of ``oracle.c`` with ``np.roll`` shifts instead of
+index loops, so that a transposed operand or a wrong neighbour in either
+implementation shows up as a disagreement on small grids.  Same readings of
+the paper as the C code (heat update of App. A; Euler scheme of App. B with
+the limiter, flux and RK2 readings listed in ``oracle.c``).
+
+Arrays are indexed [y, x] (row j, column i), x fastest in memory.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _sh(a, dx=0, dy=0):
+    """Value of the neighbour at (i+dx, j+dy) for every cell (periodic)."""
+    return np.roll(np.roll(a, -dy, axis=-2), -dx, axis=-1)
+
+
+def heat_step(T: np.ndarray, r: float) -> np.ndarray:
+    """App. A update, evaluated as (T + r*dxx) + r*dyy with dxx = (T_E - 2T) + T_W."""
+    r = T.dtype.type(r)
+    two = T + T
+    dxx = (_sh(T, 1, 0) - two) + _sh(T, -1, 0)
+    dyy = (_sh(T, 0, 1) - two) + _sh(T, 0, -1)
+    return (T + r * dxx) + r * dyy
+
+
+def heat_run(T0: np.ndarray, r: float, steps: int) -> np.ndarray:
+    T = np.array(T0, copy=True)
+    for _ in range(steps):
+        T = heat_step(T, r)
+    return T
+
+
+def laplacian(T: np.ndarray) -> np.ndarray:
+    """L T without 1/dx^2, in float64."""
+    T = T.astype(np.float64)
+    return (_sh(T, 1, 0) - 2.0 * T + _sh(T, -1, 0)) + (_sh(T, 0, 1) - 2.0 * T + _sh(T, 0, -1))
+
+
+# ----------------------------------------------------------------- Euler
+
+
+def _pressure(Q, gm1):
+    u = Q[1] / Q[0]
+    v = Q[2] / Q[0]
+    return gm1 * (Q[3] - Q.dtype.type(0.5) * (Q[1] * u + Q[2] * v))
+
+
+def _phys_flux(Q, a, gamma, gm1):
+    """Physical flux along the axis whose momentum is Q[a]; returns (F, |u_a| + c)."""
+    b = 2 if a == 1 else 1
+    rho = Q[0]
+    ua = Q[a] / rho
+    ub = Q[b] / rho
+    p = gm1 * (Q[3] - Q.dtype.type(0.5) * (Q[a] * ua + Q[b] * ub))
+    F = np.empty_like(Q)
+    F[0] = Q[a]
+    F[a] = Q[a] * ua + p
+    F[b] = Q[a] * ub
+    F[3] = (Q[3] + p) * ua
+    c = np.sqrt(gamma * p / rho)
+    return F, np.abs(ua) + c
+
+
+def _face_flux(Q, axis, gamma):
+    """Flux through the face between each cell and its +axis neighbour."""
+    t = Q.dtype.type
+    gm1 = gamma - t(1)
+    a = 1 if axis == "x" else 2
+    shift = (lambda A, k: _sh(A, k, 0)) if axis == "x" else (lambda A, k: _sh(A, 0, k))
+    p = _pressure(Q, gm1)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = (shift(p, 1) - p) / (p - shift(p, -1))  # ratio at every cell
+        rB = ratio
+        rC = shift(ratio, 1)
+        okB = (rB > 0) & (rB < np.inf)
+        okC = (rC > 0) & (rC < np.inf)
+        inv = t(1) / rB
+        phiL = t(0.5) * np.minimum(inv, t(1))
+        phiR = t(0.5) * np.minimum(rC, t(1))
+    B = Q
+    C = shift(Q, 1)
+    L = np.where(okB[None], B + phiL[None] * (C - B), B)
+    R = np.where(okC[None], C + phiR[None] * (B - C), C)
+    fL, sL = _phys_flux(L, a, gamma, gm1)
+    fR, sR = _phys_flux(R, a, gamma, gm1)
+    s = np.maximum(sL, sR)
+    return t(0.5) * ((fR + fL) + s[None] * (L - R))
+
+
+def euler_stage(Qbase, Qflux, hx, hy, gamma):
+    fx = _face_flux(Qflux, "x", gamma)
+    gy = _face_flux(Qflux, "y", gamma)
+    dF = fx - _sh(fx, -1, 0)
+    dG = gy - _sh(gy, 0, -1)
+    return (Qbase - hx * dF) - hy * dG
+
+
+def euler_run(Q0, dt, dx, dy, gamma, steps):
+    Q = np.array(Q0, copy=True)
+    t = Q.dtype.type
+    g = t(gamma)
+    hx, hy = t(0.5 * dt / dx), t(0.5 * dt / dy)
+    kx, ky = t(dt / dx), t(dt / dy)
+    for _ in range(steps):
+        Qs = euler_stage(Q, Q, hx, hy, g)
+        Q = euler_stage(Q, Qs, kx, ky, g)
+    return Q
