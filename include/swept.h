@@ -1,0 +1,157 @@
+/*
+ * swept.h -- C ABI of libswept, a two-dimensional swept-rule stencil solver
+ * for one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Walker & Niemeyer, "The Two-Dimensional Swept Rule Applied on
+ * Heterogeneous Architectures" (arXiv:2105.10332).  The swept rule solves
+ * as many (x, y, t) points of an explicit stencil time integration as the
+ * data at hand allows before exchanging anything (Sec. 3.3), in four kinds
+ * of space-time shapes: Up-Pyramid, X-/Y-Bridge, Octahedron, Down-Pyramid
+ * (Figs. 1-2).  On one GPU every shape instance is one workgroup that keeps
+ * its shape in LDS for up to b/(2n) levels between HBM round trips (Eq. 1),
+ * and every phase is one kernel launch.  The Standard solver (Sec. 3.1)
+ * takes one time step per launch.  Both use the same per-cell arithmetic,
+ * so their results are bit-identical.
+ *
+ * Problems (App. A and B), on periodic square grids of nx = ny cells:
+ *   SWEPT_HEAT   forward-Euler heat diffusion, 5-point stencil (n = 1);
+ *   SWEPT_EULER  2D compressible Euler, finite volume with a pressure-ratio
+ *                minmod limiter, Rusanov-form flux, explicit-midpoint RK2
+ *                (n = 2 per RK stage; a stage is one swept level).
+ *
+ * Memory and ownership.  The caller owns every device buffer (allocated
+ * through PyTorch or hipMalloc) and passes plain device pointers:
+ *   - the state, nvar planes of nx*ny values (nvar = 1 heat: T;
+ *     nvar = 4 Euler: rho, rho*u, rho*v, E), row-major with x fastest
+ *     (index = var*nx*ny + j*nx + i), in the problem's dtype;
+ *   - one workspace of swept_workspace_bytes() bytes.
+ * The library allocates no device memory; it owns only its host-side
+ * context.  All work is enqueued on the caller's HIP stream (hipStream_t
+ * passed as void*, NULL = default stream) and is asynchronous, except the
+ * calls documented as synchronising.  The state is advanced in place.
+ *
+ * Errors.  Every call returns 0 (SWEPT_OK) or a negative SWEPT_E* code and
+ * throws nothing.  Argument validation finishes before any HIP call.  A
+ * thread-local message describing the last error is available from
+ * swept_last_error().  Concurrent calls on one context are not allowed.
+ */
+#ifndef SWEPT_H
+#define SWEPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SWEPT_OK = 0,
+    SWEPT_EINVAL = -1,      /* null pointer or meaningless value            */
+    SWEPT_ESHAPE = -2,      /* grid/tile geometry not supported (see init)  */
+    SWEPT_EUNSTABLE = -3,   /* heat: 4r > 1, or dt <= 0                     */
+    SWEPT_ENOTSUP = -4,     /* operation not available for this problem     */
+    SWEPT_EWORKSPACE = -5,  /* workspace too small                          */
+    SWEPT_EHIP = -6,        /* HIP runtime error (message has the details)  */
+    SWEPT_ENONFINITE = -7   /* a conserved sum is NaN or infinite           */
+};
+
+enum { SWEPT_HEAT = 0, SWEPT_EULER = 1 };
+enum { SWEPT_F64 = 0, SWEPT_F32 = 1 };
+
+/* The problem as the paper states it (App. A/B; Sec. 4 parameters): grid,
+ * physical parameters and time step.  The initial state is the device
+ * buffer given to swept_init. */
+typedef struct {
+    int32_t kind;   /* SWEPT_HEAT or SWEPT_EULER                              */
+    int32_t dtype;  /* SWEPT_F64 or SWEPT_F32: state and stencil arithmetic   */
+    int32_t nx;     /* cells along x                                          */
+    int32_t ny;     /* cells along y (must equal nx)                          */
+    double lx;      /* domain length along x (heat: 1, Euler vortex: 10)      */
+    double ly;      /* domain length along y                                  */
+    double dt;      /* time step (> 0)                                        */
+    double alpha;   /* heat diffusivity; r = alpha*dt/dx^2 with dx = lx/nx    */
+    double gamma;   /* Euler ratio of specific heats (> 1)                    */
+} swept_problem;
+
+/* Launch tuning.  tile = block size b of Sec. 3.2 (0: library default);
+ * wg = threads per workgroup (0: 256; allowed 64..1024, multiple of 64). */
+typedef struct {
+    int32_t tile;
+    int32_t wg;
+} swept_tuning;
+
+/* What swept_init derived from the problem (for callers and tests). */
+typedef struct {
+    int32_t nvar;            /* 1 heat, 4 Euler                                 */
+    int32_t n;               /* stencil radius per level: heat 1, Euler 2        */
+    int32_t levels_per_step; /* heat 1, Euler 2 (RK stages)                      */
+    int32_t tile;            /* b                                                */
+    int32_t h;               /* b/(2n): levels per swept window (Eq. 1: k+1)     */
+    int32_t wg;              /* threads per workgroup                            */
+    double r;                /* heat: alpha*dt/dx^2 as used by the kernels       */
+    double dx, dy;
+    size_t state_bytes;      /* nvar*nx*ny*sizeof(scalar)                        */
+    size_t lds_bytes;        /* LDS per swept workgroup                          */
+} swept_info;
+
+typedef struct swept_ctx swept_ctx;
+
+/* Bytes of device workspace swept_init needs for this problem and tuning
+ * (a second level-parity copy of the state plus reduction scratch).
+ * Returns 0 and writes *bytes, or an error code. */
+int swept_workspace_bytes(const swept_problem* prob, const swept_tuning* tune, size_t* bytes);
+
+/* Validate the problem and create a context bound to the caller's state,
+ * workspace and stream.  Geometry rules (Sec. 3.2, Eq. 1): nx == ny;
+ * tile % (2n) == 0 and tile > 2n (b in (2n, b_max]); nx % tile == 0
+ * (arrays divisible by the block size); nx >= 2*tile; the LDS window
+ * (tile+2n)^2 * nvar * 2 levels must fit in 160 KiB.  Heat requires
+ * 4r <= 1 (SWEPT_EUNSTABLE otherwise).  No device memory is allocated. */
+int swept_init(swept_ctx** ctx, const swept_problem* prob, const swept_tuning* tune, void* d_state,
+               void* d_work, size_t work_bytes, void* hip_stream);
+
+/* Query derived parameters. */
+int swept_query(const swept_ctx* ctx, swept_info* info);
+
+/* Rebind the stream used by later calls. */
+int swept_set_stream(swept_ctx* ctx, void* hip_stream);
+
+/* Advance the state n_steps time steps with the swept rule (Sec. 3.3):
+ * one Up-Pyramid, then alternating Bridge and Octahedron phases, closing
+ * with the Down-Pyramid; one kernel launch per phase, 1 + 2*ceil(L/h)
+ * launches for L = n_steps*levels_per_step levels.  Unlike the paper,
+ * which stops at whole phases, every shape is cut at the final level, so
+ * exactly n_steps steps are taken.  In place, asynchronous. */
+int swept_advance(swept_ctx* ctx, int64_t n_steps);
+
+/* Advance n_steps with the Standard solver (Sec. 3.1): one launch per time
+ * step (Euler: both RK stages fused in one launch).  Bit-identical to
+ * swept_advance.  In place, asynchronous. */
+int standard_advance(swept_ctx* ctx, int64_t n_steps);
+
+/* Per-plane sums of the current state in double, fixed reduction order
+ * (reproducible): sum T (heat) or sum rho, rho*u, rho*v, E (Euler); out
+ * must hold nvar doubles.  Synchronises the stream.  Returns
+ * SWEPT_ENONFINITE if any sum is NaN or infinite (the values are still
+ * written). */
+int swept_conserved(swept_ctx* ctx, double* out);
+
+/* Euler time step for a CFL number: dt = cfl / max over cells of
+ * (|u|+c)/dx + (|v|+c)/dy, c = sqrt(gamma p / rho), evaluated in double.
+ * d_state is an Euler state of prob's shape and dtype; d_work needs
+ * swept_workspace_bytes(prob) bytes.  Synchronises the stream.  (The paper
+ * states no time step; this fixes one.) */
+int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, void* d_work, size_t work_bytes,
+                 void* hip_stream, double* dt_out);
+
+int swept_destroy(swept_ctx* ctx);
+
+/* Message for the last error on this thread ("" if none). */
+const char* swept_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SWEPT_H */

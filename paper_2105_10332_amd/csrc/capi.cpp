@@ -1,0 +1,334 @@
+// capi.cpp -- the C ABI of libswept (declared in include/swept.h): argument
+// validation, the phase plan of the swept rule, workspace layout and the
+// launch sequences.  Validation never touches the HIP runtime, so every
+// error path is testable without a GPU.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/swept.h"
+#include "launch.h"
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(SWEPT_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+constexpr int kParts = 1024;          // reduction partials per plane
+constexpr size_t kLdsMax = 160 * 1024; // gfx950 LDS per workgroup
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Derived {
+    int nvar, n, lps, tile, h, wg;
+    size_t scalar, state_bytes, lds_bytes;
+    double r, dx, dy;
+};
+
+size_t phase_lds(int nvar, int n, int tile, size_t scalar)
+{
+    const size_t W = (size_t)tile + 2 * n;
+    return 2 * nvar * W * W * scalar;
+}
+
+bool tile_ok(int N, int tile, int n, int nvar, size_t scalar)
+{
+    return tile > 2 * n && tile % (2 * n) == 0 && N % tile == 0 && N >= 2 * tile &&
+           phase_lds(nvar, n, tile, scalar) <= kLdsMax;
+}
+
+int default_tile(const swept_problem* p, int n, int nvar, size_t scalar)
+{
+    static const int heat_order[] = {32, 64, 16, 8, 0};
+    static const int e64_order[] = {16, 32, 8, 0};
+    static const int e32_order[] = {32, 16, 64, 8, 0};
+    const int* order = p->kind == SWEPT_HEAT ? heat_order : (p->dtype == SWEPT_F64 ? e64_order : e32_order);
+    for (int k = 0; order[k]; ++k)
+        if (tile_ok(p->nx, order[k], n, nvar, scalar)) return order[k];
+    return 0;
+}
+
+int derive(const swept_problem* p, const swept_tuning* t, Derived* d)
+{
+    if (!p) return fail(SWEPT_EINVAL, "problem is NULL");
+    if (p->kind != SWEPT_HEAT && p->kind != SWEPT_EULER) return fail(SWEPT_EINVAL, "unknown kind %d", p->kind);
+    if (p->dtype != SWEPT_F64 && p->dtype != SWEPT_F32) return fail(SWEPT_EINVAL, "unknown dtype %d", p->dtype);
+    if (p->nx <= 0 || p->ny <= 0) return fail(SWEPT_ESHAPE, "grid %d x %d is empty", p->nx, p->ny);
+    if (p->nx != p->ny) return fail(SWEPT_ESHAPE, "grid must be square (nx=%d, ny=%d)", p->nx, p->ny);
+    if (p->nx > 32768) return fail(SWEPT_ESHAPE, "nx=%d exceeds 32768", p->nx);
+    if (!(p->lx > 0) || !(p->ly > 0) || !std::isfinite(p->lx) || !std::isfinite(p->ly))
+        return fail(SWEPT_EINVAL, "domain lengths must be positive");
+    if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(SWEPT_EUNSTABLE, "dt must be positive (dt=%g)", p->dt);
+    d->nvar = p->kind == SWEPT_HEAT ? 1 : 4;
+    d->n = p->kind == SWEPT_HEAT ? 1 : 2;
+    d->lps = p->kind == SWEPT_HEAT ? 1 : 2;
+    d->scalar = p->dtype == SWEPT_F64 ? 8 : 4;
+    d->dx = p->lx / p->nx;
+    d->dy = p->ly / p->ny;
+    d->r = 0.0;
+    if (p->kind == SWEPT_HEAT) {
+        if (!(p->alpha > 0) || !std::isfinite(p->alpha)) return fail(SWEPT_EINVAL, "alpha must be positive");
+        if (d->dx != d->dy) return fail(SWEPT_ESHAPE, "heat needs dx == dy");
+        d->r = p->alpha * p->dt / (d->dx * d->dx);
+        if (4.0 * d->r > 1.0) return fail(SWEPT_EUNSTABLE, "heat: 4r = %g > 1 is unstable", 4.0 * d->r);
+    } else {
+        if (!(p->gamma > 1) || !std::isfinite(p->gamma)) return fail(SWEPT_EINVAL, "gamma must exceed 1");
+    }
+    int tile = t ? t->tile : 0;
+    if (tile == 0) {
+        tile = default_tile(p, d->n, d->nvar, d->scalar);
+        if (tile == 0) return fail(SWEPT_ESHAPE, "no supported tile for nx=%d", p->nx);
+    }
+    if (tile <= 2 * d->n || tile % (2 * d->n) != 0)
+        return fail(SWEPT_ESHAPE, "tile %d must be a multiple of 2n=%d and larger than it", tile, 2 * d->n);
+    if (p->nx % tile != 0) return fail(SWEPT_ESHAPE, "nx=%d is not divisible by tile %d", p->nx, tile);
+    if (p->nx < 2 * tile) return fail(SWEPT_ESHAPE, "nx=%d must be at least 2*tile=%d", p->nx, 2 * tile);
+    d->lds_bytes = phase_lds(d->nvar, d->n, tile, d->scalar);
+    if (d->lds_bytes > kLdsMax)
+        return fail(SWEPT_ESHAPE, "tile %d needs %zu bytes of LDS (max %zu)", tile, d->lds_bytes, kLdsMax);
+    int wg = t ? t->wg : 0;
+    if (wg == 0) wg = 256;
+    const int wg_max = p->kind == SWEPT_HEAT ? 1024 : 256;
+    if (wg < 64 || wg > wg_max || wg % 64 != 0)
+        return fail(SWEPT_EINVAL, "wg=%d must be a multiple of 64 in [64,%d]", wg, wg_max);
+    d->tile = tile;
+    d->h = tile / (2 * d->n);
+    d->wg = wg;
+    d->state_bytes = (size_t)d->nvar * p->nx * p->ny * d->scalar;
+    return SWEPT_OK;
+}
+
+size_t workspace_for(const Derived& d)
+{
+    return align_up(d.state_bytes) + align_up(sizeof(double) * 4 * kParts) + align_up(sizeof(double) * 4);
+}
+
+}  // namespace
+
+struct swept_ctx {
+    swept_problem prob;
+    Derived d;
+    void* state;
+    void* work;
+    size_t work_bytes;
+    hipStream_t stream;
+    void* buf1;
+    double* partials;
+    double* red;
+    double c[5];  // scheme constants (see PhaseArgs)
+    int std_ts;
+};
+
+extern "C" {
+
+const char* swept_last_error(void) { return g_err; }
+
+int swept_workspace_bytes(const swept_problem* prob, const swept_tuning* tune, size_t* bytes)
+{
+    if (!bytes) return fail(SWEPT_EINVAL, "bytes is NULL");
+    Derived d;
+    const int rc = derive(prob, tune, &d);
+    if (rc) return rc;
+    *bytes = workspace_for(d);
+    return SWEPT_OK;
+}
+
+int swept_init(swept_ctx** ctx, const swept_problem* prob, const swept_tuning* tune, void* d_state, void* d_work,
+               size_t work_bytes, void* hip_stream)
+{
+    if (!ctx) return fail(SWEPT_EINVAL, "ctx is NULL");
+    *ctx = nullptr;
+    Derived d;
+    int rc = derive(prob, tune, &d);
+    if (rc) return rc;
+    if (!d_state) return fail(SWEPT_EINVAL, "state pointer is NULL");
+    if (!d_work) return fail(SWEPT_EINVAL, "workspace pointer is NULL");
+    if ((reinterpret_cast<uintptr_t>(d_state) | reinterpret_cast<uintptr_t>(d_work)) % 16 != 0)
+        return fail(SWEPT_EINVAL, "state and workspace must be 16-byte aligned");
+    const size_t need = workspace_for(d);
+    if (work_bytes < need) return fail(SWEPT_EWORKSPACE, "workspace %zu bytes < %zu needed", work_bytes, need);
+    swept_ctx* c = new (std::nothrow) swept_ctx();
+    if (!c) return fail(SWEPT_EINVAL, "out of host memory");
+    c->prob = *prob;
+    c->d = d;
+    c->state = d_state;
+    c->work = d_work;
+    c->work_bytes = work_bytes;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    char* w = static_cast<char*>(d_work);
+    c->buf1 = w;
+    c->partials = reinterpret_cast<double*>(w + align_up(d.state_bytes));
+    c->red = reinterpret_cast<double*>(w + align_up(d.state_bytes) + align_up(sizeof(double) * 4 * kParts));
+    if (prob->kind == SWEPT_HEAT) {
+        c->c[0] = d.r;
+        c->c[1] = c->c[2] = c->c[3] = c->c[4] = 0.0;
+    } else {
+        c->c[0] = prob->gamma;
+        c->c[1] = 0.5 * prob->dt / d.dx;
+        c->c[2] = 0.5 * prob->dt / d.dy;
+        c->c[3] = prob->dt / d.dx;
+        c->c[4] = prob->dt / d.dy;
+    }
+    // fused Euler step tile: the largest of 16, 8, 4 dividing nx (nx is a multiple of 4 for Euler)
+    c->std_ts = (prob->nx % 16 == 0) ? 16 : (prob->nx % 8 == 0) ? 8 : 4;
+    // the dynamic-LDS ceiling is per kernel, shared by all contexts: always raise it to the maximum
+    hipError_t e = swept::set_phase_lds_limit(prob->kind, prob->dtype, kLdsMax);
+    if (e == hipSuccess && prob->kind == SWEPT_EULER) e = swept::set_euler_standard_lds_limit(prob->dtype, kLdsMax);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipFuncSetAttribute");
+    }
+    *ctx = c;
+    return SWEPT_OK;
+}
+
+int swept_query(const swept_ctx* c, swept_info* info)
+{
+    if (!c || !info) return fail(SWEPT_EINVAL, "NULL argument");
+    info->nvar = c->d.nvar;
+    info->n = c->d.n;
+    info->levels_per_step = c->d.lps;
+    info->tile = c->d.tile;
+    info->h = c->d.h;
+    info->wg = c->d.wg;
+    info->r = c->d.r;
+    info->dx = c->d.dx;
+    info->dy = c->d.dy;
+    info->state_bytes = c->d.state_bytes;
+    info->lds_bytes = c->d.lds_bytes;
+    return SWEPT_OK;
+}
+
+int swept_set_stream(swept_ctx* c, void* hip_stream)
+{
+    if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return SWEPT_OK;
+}
+
+int swept_advance(swept_ctx* c, int64_t n_steps)
+{
+    if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
+    if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
+    if (n_steps == 0) return SWEPT_OK;
+    const int64_t L64 = n_steps * c->d.lps;
+    if (L64 > (int64_t)1 << 30) return fail(SWEPT_EINVAL, "n_steps too large");
+    const int L = (int)L64;
+    const int W = (L + c->d.h - 1) / c->d.h;
+    swept::PhaseArgs a;
+    a.buf0 = c->state;
+    a.buf1 = c->buf1;
+    a.N = c->prob.nx;
+    a.tile = c->d.tile;
+    a.h = c->d.h;
+    a.tiles = c->prob.nx / c->d.tile;
+    a.L = L;
+    for (int k = 0; k < 5; ++k) a.p[k] = c->c[k];
+    for (int ph = 0; ph <= 2 * W; ++ph) {
+        a.phase = ph;
+        hipError_t e = swept::launch_phase(c->prob.kind, c->prob.dtype, a, c->d.wg, c->d.lds_bytes, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "swept phase launch");
+    }
+    if (L & 1) {  // level L lives in buffer 1
+        hipError_t e = hipMemcpyAsync(c->state, c->buf1, c->d.state_bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    return SWEPT_OK;
+}
+
+int standard_advance(swept_ctx* c, int64_t n_steps)
+{
+    if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
+    if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
+    void* bufs[2] = {c->state, c->buf1};
+    for (int64_t m = 0; m < n_steps; ++m) {
+        const void* in = bufs[m & 1];
+        void* out = bufs[(m + 1) & 1];
+        hipError_t e;
+        if (c->prob.kind == SWEPT_HEAT) {
+            e = swept::launch_heat_standard(c->prob.dtype, in, out, c->prob.nx, c->d.r, c->stream);
+        } else {
+            swept::StdArgs a;
+            a.N = c->prob.nx;
+            a.ts = c->std_ts;
+            for (int k = 0; k < 5; ++k) a.p[k] = c->c[k];
+            e = swept::launch_euler_standard(c->prob.dtype, in, out, a, c->stream);
+        }
+        if (e != hipSuccess) return hip_fail(e, "standard step launch");
+    }
+    if (n_steps & 1) {
+        hipError_t e = hipMemcpyAsync(c->state, c->buf1, c->d.state_bytes, hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    return SWEPT_OK;
+}
+
+int swept_conserved(swept_ctx* c, double* out)
+{
+    if (!c || !out) return fail(SWEPT_EINVAL, "NULL argument");
+    const size_t NN = (size_t)c->prob.nx * c->prob.ny;
+    hipError_t e = swept::launch_plane_sums(c->prob.dtype, c->state, c->d.nvar, NN, c->partials, kParts, c->red,
+                                            c->stream);
+    if (e != hipSuccess) return hip_fail(e, "plane sums");
+    e = hipMemcpyAsync(out, c->red, sizeof(double) * c->d.nvar, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(e, "plane sums copy");
+    for (int k = 0; k < c->d.nvar; ++k)
+        if (!std::isfinite(out[k])) return fail(SWEPT_ENONFINITE, "sum of plane %d is not finite", k);
+    return SWEPT_OK;
+}
+
+int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, void* d_work, size_t work_bytes,
+                 void* hip_stream, double* dt_out)
+{
+    if (!prob || !d_state || !d_work || !dt_out) return fail(SWEPT_EINVAL, "NULL argument");
+    if (prob->kind != SWEPT_EULER) return fail(SWEPT_ENOTSUP, "CFL time step is defined for Euler only");
+    if (!(cfl > 0)) return fail(SWEPT_EINVAL, "cfl must be positive");
+    swept_problem q = *prob;
+    if (!(q.dt > 0)) q.dt = 1.0;  // dt is the output here; any positive value passes validation
+    Derived d;
+    const int rc = derive(&q, nullptr, &d);
+    if (rc) return rc;
+    const size_t need = workspace_for(d);
+    if (work_bytes < need) return fail(SWEPT_EWORKSPACE, "workspace %zu bytes < %zu needed", work_bytes, need);
+    char* w = static_cast<char*>(d_work);
+    double* partials = reinterpret_cast<double*>(w + align_up(d.state_bytes));
+    double* red = reinterpret_cast<double*>(w + align_up(d.state_bytes) + align_up(sizeof(double) * 4 * kParts));
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const size_t NN = (size_t)q.nx * q.ny;
+    hipError_t e = swept::launch_cfl_max(q.dtype, d_state, NN, q.gamma, d.dx, d.dy, partials, kParts, red, st);
+    if (e != hipSuccess) return hip_fail(e, "cfl reduction");
+    double smax = 0.0;
+    e = hipMemcpyAsync(&smax, red, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "cfl copy");
+    if (!(smax > 0) || !std::isfinite(smax)) return fail(SWEPT_ENONFINITE, "max signal rate %g", smax);
+    *dt_out = cfl / smax;
+    return SWEPT_OK;
+}
+
+int swept_destroy(swept_ctx* c)
+{
+    delete c;
+    return SWEPT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,104 @@
+"""The C ABI on the CPU: the library loads, exports every symbol swept.h declares,
+and validates arguments (no HIP call happens before validation finishes)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2105_10332_amd import _lib
+from paper_2105_10332_amd._lib import CODES, Problem, Tuning
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "swept.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(?:int|const char\*)\s+(\w+)\s*\(", text)))
+
+
+def test_library_exports_all_declared_symbols():
+    L = _lib.lib()
+    names = declared_functions()
+    assert "swept_advance" in names and "standard_advance" in names and len(names) >= 10
+    for name in names:
+        assert hasattr(L, name), name
+
+
+def _ws(p, tile=0, wg=0):
+    out = ctypes.c_size_t(0)
+    rc = _lib.lib().swept_workspace_bytes(ctypes.byref(p), ctypes.byref(Tuning(tile, wg)), ctypes.byref(out))
+    return rc, out.value
+
+
+def heat(n=64, r=0.2, dtype=0):
+    dx = 1.0 / n
+    return Problem(0, dtype, n, n, 1.0, 1.0, r * dx * dx, 1.0, 1.4)
+
+
+def euler(n=64, dtype=0):
+    return Problem(1, dtype, n, n, 10.0, 10.0, 1e-3, 0.0, 1.4)
+
+
+def test_workspace_size():
+    rc, b = _ws(heat(64), 16)
+    assert rc == 0 and b >= 64 * 64 * 8
+    rc, b32 = _ws(heat(64, dtype=1), 16)
+    assert rc == 0 and b32 >= 64 * 64 * 4 and b32 < b
+    rc, be = _ws(euler(64), 16)
+    assert rc == 0 and be >= 4 * 64 * 64 * 8
+
+
+@pytest.mark.parametrize("prob,tile,wg,code", [
+    (Problem(0, 0, 64, 32, 1.0, 1.0, 1e-5, 1.0, 1.4), 16, 0, "SWEPT_ESHAPE"),      # not square
+    (heat(64), 12, 0, "SWEPT_ESHAPE"),                                             # 64 % 12
+    (heat(64), 2, 0, "SWEPT_ESHAPE"),                                              # b = 2n
+    (heat(64), 7, 0, "SWEPT_ESHAPE"),                                              # b % 2n
+    (heat(64), 64, 0, "SWEPT_ESHAPE"),                                             # N < 2b
+    (euler(64), 6, 0, "SWEPT_ESHAPE"),                                             # Euler b % 4
+    (euler(256, dtype=0), 64, 0, "SWEPT_ESHAPE"),                                  # FP64 Euler b=64: LDS
+    (heat(64, r=0.26), 16, 0, "SWEPT_EUNSTABLE"),                                  # 4r > 1
+    (Problem(0, 0, 64, 64, 1.0, 1.0, -1.0, 1.0, 1.4), 16, 0, "SWEPT_EUNSTABLE"),   # dt <= 0
+    (Problem(2, 0, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4), 16, 0, "SWEPT_EINVAL"),      # kind
+    (Problem(0, 5, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4), 16, 0, "SWEPT_EINVAL"),      # dtype
+    (Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 0.9), 16, 0, "SWEPT_EINVAL"),    # gamma <= 1
+    (heat(64), 16, 100, "SWEPT_EINVAL"),                                           # wg not multiple of 64
+    (euler(64), 16, 512, "SWEPT_EINVAL"),                                          # Euler wg > 256
+    (Problem(0, 0, 0, 0, 1.0, 1.0, 1e-5, 1.0, 1.4), 16, 0, "SWEPT_ESHAPE"),        # empty
+])
+def test_validation_codes(prob, tile, wg, code):
+    rc, _ = _ws(prob, tile, wg)
+    assert rc == CODES[code], (rc, _lib.last_error())
+    assert _lib.last_error()
+
+
+def test_fp32_euler_tile64_fits_lds():
+    rc, _ = _ws(euler(256, dtype=1), 64)
+    assert rc == 0
+
+
+def test_init_rejects_bad_pointers_and_small_workspace():
+    L = _lib.lib()
+    ctx = ctypes.c_void_p(0)
+    p = heat(64)
+    t = Tuning(16, 0)
+    _, need = _ws(p, 16)
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+    assert L.swept_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(t), None, fake, need, None) == CODES["SWEPT_EINVAL"]
+    assert L.swept_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(t), fake, None, need, None) == CODES["SWEPT_EINVAL"]
+    assert L.swept_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(t), fake, fake, need - 1, None) == \
+        CODES["SWEPT_EWORKSPACE"]
+    assert L.swept_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.byref(t), ctypes.c_void_p(0x10004), fake, need,
+                        None) == CODES["SWEPT_EINVAL"]
+    assert ctx.value is None
+    assert L.swept_advance(None, 5) == CODES["SWEPT_EINVAL"]
+    assert L.standard_advance(None, 5) == CODES["SWEPT_EINVAL"]
+
+
+def test_cfl_rejects_heat():
+    L = _lib.lib()
+    out = ctypes.c_double()
+    fake = ctypes.c_void_p(0x10000)
+    p = heat(64)
+    assert L.swept_cfl_dt(ctypes.byref(p), fake, 0.4, fake, 1 << 30, None, ctypes.byref(out)) == CODES["SWEPT_ENOTSUP"]

@@ -1,0 +1,77 @@
+"""GPU parity of the Euler path (through the C ABI)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_10332_amd import problems
+from paper_2105_10332_amd.solver import EULER, SweptSolver, swept_cfl_dt
+
+from gpu_helpers import DEV, euler_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+GAMMA = 1.4
+
+
+def _dt(Q0, n, length=10.0):
+    dx = length / n
+    return oracle.cfl_dt(Q0, dx, dx, GAMMA, 0.4)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("tile,N", [(8, 16), (8, 24), (16, 32), (16, 48), (32, 64), (12, 36)])
+def test_swept_equals_standard_and_oracle(dtype, tile, N):
+    Q0 = problems.shu_vortex(N)
+    dt = _dt(Q0, N)
+    Q0 = Q0.astype(dtype)
+    h = tile // 4
+    for steps in sorted({1, max(1, h // 2), h, h + 1, 2 * h + 3}):
+        sw = euler_gpu(Q0, dt, steps, tile, "swept")
+        st = euler_gpu(Q0, dt, steps, tile, "standard")
+        assert np.array_equal(sw, st), (tile, N, steps)
+        ref = oracle.euler_run(Q0, dt, 10.0 / N, 10.0 / N, GAMMA, steps)
+        err = rel_err(sw, ref)
+        assert err <= (1e-10 if dtype == np.float64 else 1e-5), err
+
+
+def test_poisoned_workspace_and_determinism():
+    Q0 = problems.shu_vortex(64)
+    dt = _dt(Q0, 64)
+    a = euler_gpu(Q0, dt, 13, 16, "swept", poison=True)
+    b = euler_gpu(Q0, dt, 13, 16, "swept", poison=True)
+    st = euler_gpu(Q0, dt, 13, 16, "standard")
+    assert np.isfinite(a).all() and np.array_equal(a, b) and np.array_equal(a, st)
+
+
+def test_conservation_on_gpu():
+    Q0 = problems.shu_vortex(128)
+    dt = _dt(Q0, 128)
+    Q = torch.tensor(Q0, device=DEV)
+    s = SweptSolver(EULER, Q, dt=dt, length=10.0, gamma=GAMMA, tile=16)
+    s0 = np.array(s.swept_conserved())
+    assert np.allclose(s0, oracle.plane_sums(Q0), rtol=1e-13, atol=0)
+    s.swept_advance(60)
+    s1 = np.array(s.swept_conserved())
+    scale = np.abs(Q0).reshape(4, -1).sum(axis=1)
+    assert np.all(np.abs(s1 - s0) / scale < 1e-12)
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_cfl_dt_matches_oracle_bitwise(dtype):
+    Q0 = problems.shu_vortex(256).astype(dtype)
+    dt_gpu = swept_cfl_dt(torch.tensor(Q0, device=DEV), 10.0, 0.4)
+    dt_cpu = oracle.cfl_dt(Q0, 10 / 256, 10 / 256, GAMMA, 0.4)
+    assert dt_gpu == dt_cpu
+
+
+def test_c4_full_size_short_run_vs_oracle():
+    """2048^2 vortex, FP64, CFL 0.4: 3 steps against the oracle, Swept == Standard."""
+    n = 2048
+    Q0 = problems.shu_vortex(n)
+    dt = swept_cfl_dt(torch.tensor(Q0, device=DEV), 10.0, 0.4)
+    assert abs(dt - 3.621859e-4) < 1e-9
+    sw = euler_gpu(Q0, dt, 3, 16, "swept")
+    st = euler_gpu(Q0, dt, 3, 16, "standard")
+    assert np.array_equal(sw, st)
+    ref = oracle.euler_run(Q0, dt, 10 / n, 10 / n, GAMMA, 3)
+    assert rel_err(sw, ref) <= 1e-10

@@ -1,0 +1,102 @@
+"""GPU parity of the heat path (through the C ABI): Swept == Standard bit for bit,
+both against the oracle (FP64 within 1e-10 normwise; FP32 against the FP32
+oracle and, as a stated error, against the FP64 one)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2105_10332_amd import problems
+
+from gpu_helpers import heat_gpu, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("tile,N", [(8, 16), (8, 40), (16, 32), (16, 48), (32, 64), (32, 96), (64, 128), (6, 18),
+                                    (12, 36)])
+def test_swept_equals_standard_and_oracle(dtype, tile, N):
+    h = tile // 2
+    T0 = problems.heat_sine_noise(N, seed=tile + N).astype(dtype)
+    for steps in sorted({1, h - 1, h, h + 1, 3 * h + 5}):
+        sw, r = heat_gpu(T0, 0.2, steps, tile, "swept")
+        st, _ = heat_gpu(T0, 0.2, steps, tile, "standard")
+        assert np.array_equal(sw, st), (tile, N, steps)
+        ref = oracle.heat_run(T0, r, steps)
+        if dtype == np.float64:
+            assert rel_err(sw, ref) <= 1e-10
+        else:
+            assert rel_err(sw, ref) <= 1e-6
+
+
+def test_c1_config_fp64():
+    """64^2, FP64, r = 0.2, 100 steps, sin sin + noise, 16x16 tiles (both solvers)."""
+    T0 = problems.heat_sine_noise(64)
+    sw, r = heat_gpu(T0, 0.2, 100, 16, "swept")
+    st, _ = heat_gpu(T0, 0.2, 100, 16, "standard")
+    ref = oracle.heat_run(T0, r, 100)
+    assert np.array_equal(sw, st)
+    err = rel_err(sw, ref)
+    print(f"C1 fp64 swept vs oracle: {err:.3e}")
+    assert err <= 1e-10
+
+
+def test_fp32_matches_fp32_oracle_and_states_fp64_error():
+    T0 = problems.heat_fourier_modes(128)
+    sw, r = heat_gpu(T0.astype(np.float32), 0.2, 300, 32, "swept")
+    o32 = oracle.heat_run(T0.astype(np.float32), r, 300)
+    o64 = oracle.heat_run(T0, r, 300)
+    assert rel_err(sw, o32) <= 1e-6
+    e64 = rel_err(sw, o64)
+    print(f"FP32 GPU vs FP64 oracle (128^2, 300 steps): {e64:.3e}")
+    assert e64 < 1e-4
+
+
+def test_zero_steps_is_identity():
+    T0 = problems.heat_sine_noise(32)
+    sw, _ = heat_gpu(T0, 0.2, 0, 16, "swept")
+    assert np.array_equal(sw, T0)
+
+
+def test_poisoned_workspace_and_determinism():
+    """All-NaN workspace: a stale read would surface as NaN; two runs agree bitwise."""
+    T0 = problems.heat_sine_noise(96, seed=5)
+    a, _ = heat_gpu(T0, 0.24, 77, 32, "swept", poison=True)
+    b, _ = heat_gpu(T0, 0.24, 77, 32, "swept", poison=True)
+    st, _ = heat_gpu(T0, 0.24, 77, 32, "standard")
+    assert np.isfinite(a).all()
+    assert np.array_equal(a, b) and np.array_equal(a, st)
+
+
+@pytest.mark.parametrize("wg", [64, 512, 1024])
+def test_workgroup_sizes(wg):
+    T0 = problems.heat_sine_noise(128, seed=wg)
+    a, _ = heat_gpu(T0, 0.2, 41, 64, "swept", wg=wg)
+    st, _ = heat_gpu(T0, 0.2, 41, 64, "standard")
+    assert np.array_equal(a, st)
+
+
+@pytest.mark.parametrize("dtype,tile", [(np.float64, 16), (np.float64, 32), (np.float64, 64), (np.float32, 32)])
+def test_c2_full_size_closed_form(dtype, tile):
+    """4096^2, r = 0.2, 1000 steps, 16 Fourier modes: Swept equals Standard, and sampled
+    cells equal the exact discrete solution sum a G^M cos(...) (P2)."""
+    n, M = 4096, 1000
+    modes = problems.fourier_modes(problems.SEED_HEAT_MODES)
+    T0 = modes.field(n).astype(dtype)
+    sw, r = heat_gpu(T0, 0.2, M, tile, "swept")
+    if tile == 32:
+        st, _ = heat_gpu(T0, 0.2, M, tile, "standard")
+        assert np.array_equal(sw, st)
+    G = np.array([1 - 4 * r * (math.sin(math.pi * p / n) ** 2 + math.sin(math.pi * q / n) ** 2)
+                  for p, q in zip(modes.p, modes.q)])
+    rng = np.random.default_rng(9)
+    js, is_ = rng.integers(0, n, 400), rng.integers(0, n, 400)
+    x = (np.arange(n) + 0.5) / n
+    exact = np.zeros(400)
+    for p, q, a, ph, g in zip(modes.p, modes.q, modes.a, modes.phi, G):
+        exact += a * g ** M * np.cos(2 * math.pi * (p * x[is_] + q * x[js]) + ph)
+    err = np.abs(sw[js, is_] - exact).max() / np.abs(T0).max()
+    print(f"C2 {np.dtype(dtype).name} b={tile}: closed-form error {err:.3e}")
+    assert err < (1e-12 if dtype == np.float64 else 2e-5)
