@@ -24,7 +24,12 @@
  *   - the state, nvar planes of nx*ny values (nvar = 1 heat: T;
  *     nvar = 4 Euler: rho, rho*u, rho*v, E), row-major with x fastest
  *     (index = var*nx*ny + j*nx + i), in the problem's dtype;
- *   - one workspace of swept_workspace_bytes() bytes.
+ *   - one workspace of swept_workspace_bytes() bytes: the second
+ *     level-parity copy of the state (its first state_bytes bytes), reduction
+ *     scratch and a per-level launch table written by swept_init.  It belongs
+ *     to the library from swept_init to swept_destroy: the caller must not
+ *     write it in between (its first state_bytes bytes may be overwritten
+ *     freely between calls; they are scratch).
  * The library allocates no device memory; it owns only its host-side
  * context.  All work is enqueued on the caller's HIP stream (hipStream_t
  * passed as void*, NULL = default stream) and is asynchronous, except the

@@ -116,9 +116,49 @@ int derive(const swept_problem* p, const swept_tuning* t, Derived* d)
     return SWEPT_OK;
 }
 
+size_t table_bytes(const Derived& d) { return sizeof(swept::LevelEntry) * swept::level_table_entries(d.h); }
+
 size_t workspace_for(const Derived& d)
 {
-    return align_up(d.state_bytes) + align_up(sizeof(double) * 4 * kParts) + align_up(sizeof(double) * 4);
+    return align_up(d.state_bytes) + align_up(sizeof(double) * 4 * kParts) + align_up(sizeof(double) * 4) +
+           align_up(table_bytes(d));
+}
+
+int half_width_host(int t, int h, int n)
+{
+    if (t < 1 || t > 2 * h - 1) return 0;
+    return n * (t < 2 * h - t ? t : 2 * h - t);
+}
+
+// Host copy of the per-level table (see launch.h).  t is the level within
+// the shape's window; Bridges' shrinking axis is at t + h.
+void build_level_table(const Derived& d, swept::LevelEntry* tab)
+{
+    const int h = d.h, n = d.n, C = d.tile / 2 + n;
+    for (int k = 0; k < swept::level_table_entries(h); ++k) tab[k] = swept::LevelEntry{};
+    auto fill = [&](swept::LevelEntry& e, int hx, int hy, int hx2, int hy2) {
+        e.x0 = C - hx;
+        e.y0 = C - hy;
+        e.fw = 2 * hx;
+        e.fh = 2 * hy;
+        const int cells = e.fw * e.fh;
+        e.R = cells <= d.wg ? 1 : (cells + d.wg - 1) / d.wg;
+        e.spc = (e.fh + e.R - 1) / e.R;
+        e.hx2 = hx2;
+        e.hy2 = hy2;
+        e.inv_fw = e.fw > 0 ? 1.0f / (float)e.fw : 0.0f;
+    };
+    for (int t = 1; t <= 2 * h - 1; ++t) {  // Octahedron
+        const int hw = half_width_host(t, h, n), hw2 = half_width_host(t + 2, h, n);
+        fill(tab[t], hw, hw, hw2, hw2);
+    }
+    for (int t = 1; t <= h - 1; ++t) {  // Bridges: growing axis t, shrinking axis t + h
+        const int g = half_width_host(t, h, n), s = half_width_host(t + h, h, n);
+        const bool has2 = t + 2 <= h - 1;
+        const int g2 = has2 ? half_width_host(t + 2, h, n) : 0, s2 = has2 ? half_width_host(t + 2 + h, h, n) : 0;
+        fill(tab[2 * h + t], g, s, g2, s2);  // X-Bridge (w, w-1): x grows
+        fill(tab[3 * h + t], s, g, s2, g2);  // Y-Bridge (w-1, w): y grows
+    }
 }
 
 }  // namespace
@@ -135,6 +175,7 @@ struct swept_ctx {
     double* red;
     double c[5];  // scheme constants (see PhaseArgs)
     int std_ts;
+    swept::LevelEntry* tab_dev;  // level table inside the workspace
 };
 
 extern "C" {
@@ -189,12 +230,31 @@ int swept_init(swept_ctx** ctx, const swept_problem* prob, const swept_tuning* t
     }
     // fused Euler step tile: the largest of 16, 8, 4 dividing nx (nx is a multiple of 4 for Euler)
     c->std_ts = (prob->nx % 16 == 0) ? 16 : (prob->nx % 8 == 0) ? 8 : 4;
+    c->tab_dev = reinterpret_cast<swept::LevelEntry*>(w + align_up(d.state_bytes) +
+                                                      align_up(sizeof(double) * 4 * kParts) +
+                                                      align_up(sizeof(double) * 4));
     // the dynamic-LDS ceiling is per kernel, shared by all contexts: always raise it to the maximum
     hipError_t e = swept::set_phase_lds_limit(prob->kind, prob->dtype, kLdsMax);
     if (e == hipSuccess && prob->kind == SWEPT_EULER) e = swept::set_euler_standard_lds_limit(prob->dtype, kLdsMax);
     if (e != hipSuccess) {
         delete c;
         return hip_fail(e, "hipFuncSetAttribute");
+    }
+    {
+        const int ne = swept::level_table_entries(d.h);
+        swept::LevelEntry* host = new (std::nothrow) swept::LevelEntry[ne];
+        if (!host) {
+            delete c;
+            return fail(SWEPT_EINVAL, "out of host memory");
+        }
+        build_level_table(d, host);
+        e = hipMemcpyAsync(c->tab_dev, host, table_bytes(d), hipMemcpyHostToDevice, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        delete[] host;
+        if (e != hipSuccess) {
+            delete c;
+            return hip_fail(e, "level table upload");
+        }
     }
     *ctx = c;
     return SWEPT_OK;
@@ -241,6 +301,7 @@ int swept_advance(swept_ctx* c, int64_t n_steps)
     a.h = c->d.h;
     a.tiles = c->prob.nx / c->d.tile;
     a.L = L;
+    a.tab = c->tab_dev;
     for (int k = 0; k < 5; ++k) a.p[k] = c->c[k];
     for (int ph = 0; ph <= 2 * W; ++ph) {
         a.phase = ph;

@@ -9,16 +9,19 @@
 // w = 0 and, cut at the final level, the Down-Pyramid -- and phase 2w-1 runs
 // the two Bridges (w, w-1), (w-1, w) of window w in the same launch.
 //
-// Memory protocol (level l of a cell lives in global buffer l mod 2).  For
-// each level l of its shape a workgroup
-//   1. loads Box(F(l), n) minus F(l-1), at level l-1, from buffer (l-1)%2
-//      into LDS buffer (l-1)%2 (F = footprint rectangle of the level);
-//   2. computes F(l) into LDS buffer l%2 (Euler's second stage also reads
-//      the cell's own level l-2 value from LDS buffer l%2, in place);
-//   3. stores the cells of F(l) that are not in F(l+2) to buffer l%2:
-//      exactly the values later shapes read.
-// The load for l+1 is issued right after the compute of l (it touches only
-// cells outside F(l)), so each level costs one barrier.
+// Memory protocol (level l of a cell lives in global buffer l mod 2).  Level l
+// of a shape needs ring(l) = Box(F(l), n) minus F(l-1) at level l-1 from
+// outside (F = footprint rectangle of the level, Box = grown by n); every
+// ring was written by earlier phases, and the rings of one level parity are
+// disjoint, so a workgroup
+//   1. loads all its rings up front, ring(l) from buffer (l-1)%2 into LDS
+//      buffer (l-1)%2, in one pass over its (b+2n)^2 window -- one memory
+//      latency per shape instead of one per level;
+//   2. computes each level l of F(l) into LDS buffer l%2 (Euler's second
+//      stage also reads the cell's own level l-2 value there, in place), one
+//      barrier per level;
+//   3. stores the cells of F(l) that are not in F(l+2) to buffer l%2: each
+//      cell's top two levels, exactly the values later shapes read.
 #include <hip/hip_runtime.h>
 
 #include "launch.h"
@@ -52,54 +55,88 @@ __device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
     return n * (t < 2 * h - t ? t : 2 * h - t);
 }
 
-// Load the ring Box(bx0..bx1, by0..by1) minus hole (hx0..hx1, hy0..hy1),
-// local window coordinates, from global buffer g (planes of NN values) into
-// the LDS buffer l (planes of P values, row stride W).  An empty hole is
-// given as hx0 == hx1.
-template <int NVAR, typename T>
-__device__ __forceinline__ void load_ring(T* __restrict__ l, const T* __restrict__ g, int W, int P, int N, size_t NN,
-                                          int ox, int oy, int bx0, int bx1, int by0, int by1, int hx0, int hx1,
-                                          int hy0, int hy1)
+// Which level-parity buffers the up-front load fills at local cell (lx, ly):
+// bit p set <=> the cell lies in a ring(l) = Box(F(l), n) minus F(l-1) with
+// (l-1)%2 == p.  With t = l - (w-1)h and a the cell's distance index from
+// the centre along a growing axis (inside <=> a < hw), ring(t) holds
+// (t-1)n <= a < (t+1)n, so the candidates t = a/n and a/n + 1 have opposite
+// parities:
+//   Octahedron w >= 1: a = max(ax, ay), t <= min(h, tmax);
+//   Bridge: a along the growing axis, t <= min(h-1, tmax), and the shrinking
+//     axis must satisfy s < (h-t+1)n;
+//   Up-Pyramid (w = 0): only its first level, the tile at level 0;
+// tmax = hi - (w-1)h (the cut at the final level).  A two-stage scheme whose
+// first level is even also needs F(lo) at level lo-2 (buffer lo%2).
+template <int R, int TWO_STAGE>
+__device__ __forceinline__ int ring_parities(int wx, int wy, int lo, int hi, int h, int b, int C, int lx, int ly)
 {
-    if (hx0 >= hx1) {  // no hole: the whole box as the top region
-        hy0 = hy1 = by1;
-        hx0 = hx1 = bx1;
+    const int ax = lx >= C ? lx - C : C - 1 - lx;
+    const int ay = ly >= C ? ly - C : C - 1 - ly;
+    const int wmax = wx > wy ? wx : wy;
+    if (wmax == 0) return (ax < b / 2 && ay < b / 2) ? 1 : 0;
+    const int base = (wmax - 1) * h;
+    const int tmax = hi - base;
+    int a, s, tcap;
+    if (wx == wy) {
+        a = ax > ay ? ax : ay;
+        s = -1;  // no shrinking axis
+        tcap = h < tmax ? h : tmax;
+    } else {
+        a = wx > wy ? ax : ay;
+        s = wx > wy ? ay : ax;
+        tcap = (h - 1) < tmax ? (h - 1) : tmax;
     }
-    const int bw = bx1 - bx0;
-    const int n_top = bw * (hy0 - by0);
-    const int n_bot = bw * (by1 - hy1);
-    const int sh = hy1 - hy0;
-    const int swl = hx0 - bx0, swr = bx1 - hx1;
-    const int n_l = swl * sh, n_r = swr * sh;
-    const int total = n_top + n_bot + n_l + n_r;
-    const float inv_bw = 1.0f / (float)(bw > 0 ? bw : 1);
-    const float inv_l = 1.0f / (float)(swl > 0 ? swl : 1);
-    const float inv_r = 1.0f / (float)(swr > 0 ? swr : 1);
-    for (int i = threadIdx.x; i < total; i += blockDim.x) {
-        int lx, ly, k = i;
-        if (k < n_top) {
-            const int q = qdiv(k, inv_bw);
-            ly = by0 + q;
-            lx = bx0 + (k - q * bw);
-        } else if ((k -= n_top) < n_bot) {
-            const int q = qdiv(k, inv_bw);
-            ly = hy1 + q;
-            lx = bx0 + (k - q * bw);
-        } else if ((k -= n_bot) < n_l) {
-            const int q = qdiv(k, inv_l);
-            ly = hy0 + q;
-            lx = bx0 + (k - q * swl);
-        } else {
-            k -= n_l;
-            const int q = qdiv(k, inv_r);
-            ly = hy0 + q;
-            lx = hx1 + (k - q * swr);
-        }
-        const int gx = wrapi(ox + lx, N), gy = wrapi(oy + ly, N);
-        const size_t gi = (size_t)gy * N + gx;
-        const int li = ly * W + lx;
+    const int t1 = a / R;
+    int m = 0;
 #pragma unroll
-        for (int v = 0; v < NVAR; ++v) l[v * P + li] = g[v * NN + gi];
+    for (int k = 0; k < 2; ++k) {
+        const int t = t1 + k;
+        if (t >= 1 && t <= tcap && s < (h - t + 1) * R) m |= 1 << ((base + t - 1) & 1);
+    }
+    if (TWO_STAGE && (lo & 1) == 0 && ax < half_width(wx, lo, h, R) && ay < half_width(wy, lo, h, R))
+        m |= 1 << (lo & 1);
+    return m;
+}
+
+// Up-front load of every ring of the shape: a strided pass over the window,
+// KB cells per thread per batch with all their loads issued before any LDS
+// write, so the batch costs one memory latency.
+template <class S, typename T>
+__device__ __forceinline__ void preload_rings(T* lds, int BUF, const T* g0, const T* g1, int W, int P, int N,
+                                              size_t NN, int ox, int oy, int wx, int wy, int lo, int hi, int h, int C)
+{
+    constexpr int NVAR = S::NVAR, KB = 4;
+    const int cnt = W * W;
+    const float invW = 1.0f / (float)W;
+    for (int base = 0; base < cnt; base += KB * (int)blockDim.x) {
+        T v[KB][2][NVAR];
+        int li[KB], pm[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
+            pm[k] = 0;
+            li[k] = i;
+            if (i < cnt) {
+                const int ly = qdiv(i, invW), lx = i - ly * W;
+                pm[k] = ring_parities<S::R, S::TWO_STAGE>(wx, wy, lo, hi, h, W - 2 * S::R, C, lx, ly);
+                if (pm[k]) {
+                    const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
+                    if (pm[k] & 1)
+#pragma unroll
+                        for (int c = 0; c < NVAR; ++c) v[k][0][c] = g0[c * NN + gi];
+                    if (pm[k] & 2)
+#pragma unroll
+                        for (int c = 0; c < NVAR; ++c) v[k][1][c] = g1[c * NN + gi];
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+                if (pm[k] & (1 << p))
+#pragma unroll
+                    for (int c = 0; c < NVAR; ++c) lds[p * BUF + c * P + li[k]] = v[k][p][c];
     }
 }
 
@@ -142,6 +179,43 @@ __device__ __forceinline__ void cell_update<EulerS, float>(const float* prev, co
     euler_update<float>(prev, cur, li, W, P, lvl, a, out);
 }
 
+// One heat level on the footprint [C-hx, C+hx) x [C-hy, C+hy) of the window:
+// each thread takes a vertical strip of R cells of one column (R chosen so
+// the footprint spreads over the whole workgroup) and walks it top to
+// bottom, keeping the vertical neighbours in registers: about three LDS
+// reads per cell-update.  Cells outside F(l+2) (half-widths hx2, hy2) are
+// also written to the level's global buffer.
+template <typename T>
+__device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ gout,
+                                           int W, int C, const LevelEntry& e, int hx2, int hy2, int ox, int oy,
+                                           int N, T r)
+{
+    const int fw = e.fw, nthr = blockDim.x;
+    for (int t = threadIdx.x; t < fw * e.spc; t += nthr) {
+        const int sidx = qdiv(t, e.inv_fw);
+        const int x = e.x0 + (t - sidx * fw);
+        const int ys = e.y0 + sidx * e.R;
+        const int ye = min(ys + e.R, e.y0 + e.fh);
+        const bool xkeep = (x - C >= -hx2) && (x - C < hx2);
+        const int gx = wrapi(ox + x, N);
+        int gy = wrapi(oy + ys, N);
+        int li = ys * W + x;
+        T up = prev[li - W];
+        T c = prev[li];
+        for (int y = ys; y < ye; ++y) {
+            const T dn = prev[li + W];
+            const T v = heat_update<T>(c, prev[li + 1], prev[li - 1], dn, up, r);
+            cur[li] = v;
+            const bool keep = xkeep && (y - C >= -hy2) && (y - C < hy2);
+            if (!keep) gout[(size_t)gy * N + gx] = v;
+            up = c;
+            c = dn;
+            li += W;
+            gy = (gy + 1 == N) ? 0 : gy + 1;
+        }
+    }
+}
+
 template <class S, typename T>
 __global__ void __launch_bounds__(S::MAXWG) swept_phase_kernel(PhaseArgs a)
 {
@@ -174,49 +248,50 @@ __global__ void __launch_bounds__(S::MAXWG) swept_phase_kernel(PhaseArgs a)
     const int cx = jx * b + ((wx & 1) ? 0 : b / 2);
     const int cy = jy * b + ((wy & 1) ? 0 : b / 2);
     const int ox = cx - C, oy = cy - C;
-    T* g[2] = {reinterpret_cast<T*>(a.buf0), reinterpret_cast<T*>(a.buf1)};
-    T* lb[2] = {lds, lds + NVAR * P};
+    T* g0 = reinterpret_cast<T*>(a.buf0);
+    T* g1 = reinterpret_cast<T*>(a.buf1);
+    const int BUF = NVAR * P;  // LDS values per level-parity buffer (address arithmetic keeps ds_* access)
 
-    // first level: whole Box(F(lo), R) at level lo-1
-    {
-        const int hx = half_width(wx, lo, h, R), hy = half_width(wy, lo, h, R);
-        load_ring<NVAR, T>(lb[(lo - 1) & 1], g[(lo - 1) & 1], W, P, N, NN, ox, oy, C - hx - R, C + hx + R,
-                           C - hy - R, C + hy + R, 0, 0, 0, 0);
-        if (S::TWO_STAGE && (lo & 1) == 0)  // own cells at level lo-2 for the second RK stage
-            load_ring<NVAR, T>(lb[lo & 1], g[lo & 1], W, P, N, NN, ox, oy, C - hx, C + hx, C - hy, C + hy, 0, 0,
-                               0, 0);
-    }
+    preload_rings<S, T>(lds, BUF, g0, g1, W, P, N, NN, ox, oy, wx, wy, lo, hi, h, C);
     __syncthreads();
 
+    // level table of this shape type, indexed by the level within its window
+    const LevelEntry* tab;
+    int kbase;
+    if (wx == wy) {
+        tab = a.tab;
+        kbase = wx == 0 ? -h : (wx - 1) * h;  // the Up-Pyramid is the Octahedron's upper half
+    } else {
+        tab = a.tab + (wx > wy ? 2 * h : 3 * h);
+        kbase = (wmax - 1) * h;
+    }
     for (int lvl = lo; lvl <= hi; ++lvl) {
-        const int hx = half_width(wx, lvl, h, R), hy = half_width(wy, lvl, h, R);
-        const int hx2 = (lvl + 2 <= hi) ? half_width(wx, lvl + 2, h, R) : 0;
-        const int hy2 = (lvl + 2 <= hi) ? half_width(wy, lvl + 2, h, R) : 0;
-        const int fw = 2 * hx, cnt = fw * 2 * hy;
-        const float inv_fw = 1.0f / (float)fw;
-        const T* prev = lb[(lvl - 1) & 1];
-        T* cur = lb[lvl & 1];
-        T* gout = g[lvl & 1];
-        for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-            const int q = qdiv(i, inv_fw);
-            const int ly = C - hy + q, lx = C - hx + (i - q * fw);
-            const int li = ly * W + lx;
-            T out[NVAR];
-            cell_update<S, T>(prev, cur, li, W, P, lvl, a, out);
+        const LevelEntry e = tab[lvl - kbase];
+        const bool has2 = lvl + 2 <= hi;
+        const int hx2 = has2 ? e.hx2 : 0, hy2 = has2 ? e.hy2 : 0;
+        const T* prev = lds + ((lvl - 1) & 1) * BUF;
+        T* cur = lds + (lvl & 1) * BUF;
+        T* gout = (lvl & 1) ? g1 : g0;
+        if constexpr (NVAR == 1) {
+            heat_level<T>(prev, cur, gout, W, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
+        } else {
+            const int fw = e.fw, cnt = fw * e.fh;
+            for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+                const int q = qdiv(i, e.inv_fw);
+                const int ly = e.y0 + q, lx = e.x0 + (i - q * fw);
+                const int li = ly * W + lx;
+                T out[NVAR];
+                cell_update<S, T>(prev, cur, li, W, P, lvl, a, out);
 #pragma unroll
-            for (int v = 0; v < NVAR; ++v) cur[v * P + li] = out[v];
-            const int dx = lx - C, dy = ly - C;  // in F(l+2) <=> -hw2 <= d < hw2
-            const bool keep = (dx >= -hx2) && (dx < hx2) && (dy >= -hy2) && (dy < hy2);
-            if (!keep) {
-                const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
+                for (int v = 0; v < NVAR; ++v) cur[v * P + li] = out[v];
+                const int dx = lx - C, dy = ly - C;  // in F(l+2) <=> -hw2 <= d < hw2
+                const bool keep = (dx >= -hx2) && (dx < hx2) && (dy >= -hy2) && (dy < hy2);
+                if (!keep) {
+                    const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
 #pragma unroll
-                for (int v = 0; v < NVAR; ++v) gout[v * NN + gi] = out[v];
+                    for (int v = 0; v < NVAR; ++v) gout[v * NN + gi] = out[v];
+                }
             }
-        }
-        if (lvl < hi) {  // ring for level l+1: Box(F(l+1), R) minus F(l), at level l
-            const int nx_ = half_width(wx, lvl + 1, h, R), ny_ = half_width(wy, lvl + 1, h, R);
-            load_ring<NVAR, T>(cur, gout, W, P, N, NN, ox, oy, C - nx_ - R, C + nx_ + R, C - ny_ - R, C + ny_ + R,
-                               C - hx, C + hx, C - hy, C + hy);
         }
         __syncthreads();
     }

@@ -7,6 +7,23 @@
 
 namespace swept {
 
+// Per-level launch geometry of one shape type, precomputed on the host
+// (uniform across a workgroup, read with scalar loads).  Footprint
+// [x0, x0+fw) x [y0, y0+fh) in window coordinates; hx2/hy2 = half-widths of
+// the footprint two levels up (0 past the shape's end); R = cells per thread
+// strip and spc = strips per column for the heat strip mapping; inv_fw =
+// 1.0f/fw for the exact float quotient.
+struct LevelEntry {
+    int x0, y0, fw, fh, R, spc, hx2, hy2;
+    float inv_fw;
+    int pad[3];
+};
+
+// Level table layout (entries indexed by t, the level within the shape's
+// window): Octahedron t = 1..2h-1 at [t] (the Up-Pyramid is its upper half,
+// t = l + h); X-Bridge (w, w-1) t = 1..h-1 at [2h + t]; Y-Bridge at [3h + t].
+inline int level_table_entries(int h) { return 4 * h; }
+
 // Arguments of one swept phase launch.  p[] holds the scheme constants in
 // double: heat {r}; Euler {gamma, dt/(2dx), dt/(2dy), dt/dx, dt/dy}.
 struct PhaseArgs {
@@ -18,6 +35,7 @@ struct PhaseArgs {
     int tiles;    // N / b
     int L;        // final level of this advance
     int phase;    // 0 .. 2*ceil(L/h)
+    const LevelEntry* tab;  // level table (device memory, see above)
     double p[5];
 };
 

@@ -1,0 +1,133 @@
+"""Autotuner for the swept solver: picks the tile edge b (which fixes the swept
+depth k = b/(2n) - 1 levels per window, Eq. 1) and the workgroup size by
+timing candidates on the GPU, and caches the winner as JSON.
+
+The paper finds the best block size hardware- and problem-dependent and
+recommends tuning (Sec. 5-6); this automates that per (problem kind,
+precision, grid edge, GPU architecture).  Cache location: $SWEPT_TUNE_CACHE
+or tune_cache.json next to this file.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LDS_MAX = 160 * 1024
+
+
+def cache_path() -> str:
+    return os.environ.get("SWEPT_TUNE_CACHE", os.path.join(HERE, "tune_cache.json"))
+
+
+def _arch() -> str:
+    try:
+        import torch
+
+        if torch.cuda.is_available():
+            return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        pass
+    return "gfx950"
+
+
+def _key(kind: str, dtype: str, n: int, arch: str | None = None) -> str:
+    return f"{kind}/{dtype}/{n}/{arch or _arch()}"
+
+
+def load_cache() -> dict:
+    try:
+        with open(cache_path()) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def save_cache(c: dict):
+    p = cache_path()
+    tmp = p + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(c, f, indent=1, sort_keys=True)
+    os.replace(tmp, p)
+
+
+def candidates(kind: str, dtype: str, n: int):
+    """Valid tiles (b > 2n, b % 2n == 0, n_grid % b == 0, n_grid >= 2b, LDS fits) x workgroup sizes."""
+    rad = 1 if kind == "heat" else 2
+    nvar = 1 if kind == "heat" else 4
+    S = 8 if dtype == "f64" else 4
+    tiles = []
+    for b in (8, 12, 16, 24, 32, 48, 64):
+        if b <= 2 * rad or b % (2 * rad) or n % b or n < 2 * b:
+            continue
+        if 2 * nvar * (b + 2 * rad) ** 2 * S > LDS_MAX:
+            continue
+        tiles.append(b)
+    wgs = (256, 512, 1024) if kind == "heat" else (128, 256)
+    return [(b, wg) for b in tiles for wg in wgs]
+
+
+def default_tile(kind: str, dtype: str, n: int) -> int:
+    order = {"heat": (32, 64, 16, 8), "euler": (16, 32, 8) if dtype == "f64" else (32, 16, 64, 8)}[kind]
+    valid = {b for b, _ in candidates(kind, dtype, n)}
+    for b in order:
+        if b in valid:
+            return b
+    return min(valid) if valid else 0
+
+
+def best(kind: str, dtype: str, n: int):
+    """(tile, wg) from the cache, else the heuristic default (wg 0 = library default)."""
+    e = load_cache().get(_key(kind, dtype, n))
+    if e:
+        return int(e["tile"]), int(e["wg"])
+    return default_tile(kind, dtype, n), 0
+
+
+def best_tile(kind: str, dtype: str, n: int) -> int:
+    return best(kind, dtype, n)[0]
+
+
+def tune(kind: str, dtype: str, n: int, steps: int = 0, reps: int = 2, save: bool = True, verbose: bool = False):
+    """Time every candidate on the GPU (swept advance of `steps` steps, default a few
+    windows of the deepest tile) and cache the fastest."""
+    import torch
+
+    from . import problems
+    from .solver import EULER, HEAT, SweptSolver
+
+    dev = torch.device("cuda", 0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    if kind == "heat":
+        x0 = torch.tensor(problems.heat_fourier_modes(n), dtype=tdt, device=dev)
+        mk = lambda b, wg, x: SweptSolver(HEAT, x, dt=0.2 / n / n, length=1.0, alpha=1.0, tile=b, wg=wg)
+        steps = steps or 128
+    else:
+        x0 = torch.tensor(problems.shu_vortex(n), dtype=tdt, device=dev)
+        mk = lambda b, wg, x: SweptSolver(EULER, x, dt=0.4 * (10.0 / n) / 6.0, length=10.0, tile=b, wg=wg)
+        steps = steps or 32
+    results = []
+    for b, wg in candidates(kind, dtype, n):
+        x = x0.clone()
+        s = mk(b, wg, x)
+        s.swept_advance(steps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            s.swept_advance(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        results.append((ms, b, wg))
+        if verbose:
+            print(f"tune {kind} {dtype} n={n}: tile {b} wg {wg}: {ms:.3f} ms", flush=True)
+        s.close()
+    results.sort()
+    ms, b, wg = results[0]
+    if save:
+        c = load_cache()
+        c[_key(kind, dtype, n)] = {"tile": b, "wg": wg, "ms": ms, "steps": steps,
+                                   "all": [[r[1], r[2], round(r[0], 4)] for r in results]}
+        save_cache(c)
+    return b, wg, results

@@ -16,8 +16,8 @@ def heat_gpu(T0: np.ndarray, r: float, steps: int, tile: int, method: str = "swe
     T = torch.tensor(T0, device=DEV)
     dx = 1.0 / n
     s = SweptSolver(HEAT, T, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, wg=wg)
-    if poison:
-        s.work.fill_(255)  # all-ones bytes: NaN in every float lane of the workspace
+    if poison:  # all-ones bytes = NaN in every lane of the second level-parity buffer
+        s.work[: s.info.state_bytes].fill_(255)
     getattr(s, method + "_advance")(steps)
     torch.cuda.synchronize()
     r_used = s.info.r
@@ -30,7 +30,7 @@ def euler_gpu(Q0: np.ndarray, dt: float, steps: int, tile: int, method: str = "s
     Q = torch.tensor(Q0, device=DEV)
     s = SweptSolver(EULER, Q, dt=dt, length=length, gamma=1.4, tile=tile)
     if poison:
-        s.work.fill_(255)
+        s.work[: s.info.state_bytes].fill_(255)
     getattr(s, method + "_advance")(steps)
     torch.cuda.synchronize()
     s.close()

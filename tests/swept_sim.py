@@ -137,8 +137,10 @@ class ProtocolError(AssertionError):
 class SweptSim:
     """Executes the swept schedule with the GPU memory protocol on the CPU."""
 
-    def __init__(self, g: Geom, kind: str, params: dict, dtype=np.float64, store_lag: int = 2):
+    def __init__(self, g: Geom, kind: str, params: dict, dtype=np.float64, store_lag: int = 2,
+                 preload: bool = False):
         self.store_lag = store_lag  # stores F(l) minus F(l+store_lag); 2 is the protocol
+        self.preload = preload      # issue every level's loads before the first compute
         self.g = g
         self.kind = kind
         self.p = params
@@ -209,16 +211,33 @@ class SweptSim:
                                 ltag[dst][y, x] = lvl if ok else -2
                             nload += len(ys)
 
+                        def level_loads(lvl):
+                            F = g.footprint(wx, wy, jx, jy, lvl)
+                            prevmask = rect_mask(g.footprint(wx, wy, jx, jy, lvl - 1)) if lvl > lo else \
+                                np.zeros((W, W), bool)
+                            out = [(rect_mask(F, g.n) & ~prevmask, lvl - 1)]
+                            if two_stage and lvl % 2 == 0 and lvl == lo:
+                                out.append((rect_mask(F), lvl - 2))
+                            return out
+
+                        if self.preload:
+                            # every level's loads first; within one LDS parity buffer they must not overlap
+                            placed = [np.zeros((W, W), bool), np.zeros((W, W), bool)]
+                            for lvl in range(lo, hi + 1):
+                                for mask, src in level_loads(lvl):
+                                    if np.any(placed[src % 2] & mask):
+                                        raise ProtocolError(f"{inst}: preloaded rings overlap in LDS buffer {src % 2}")
+                                    placed[src % 2] |= mask
+                                    load(mask, src, src % 2)
+                            self.preloaded = placed
                         for lvl in range(lo, hi + 1):
                             F = g.footprint(wx, wy, jx, jy, lvl)
                             if F is None:
                                 continue
                             fmask = rect_mask(F)
-                            prevmask = rect_mask(g.footprint(wx, wy, jx, jy, lvl - 1)) if lvl > lo else \
-                                np.zeros((W, W), bool)
-                            load(rect_mask(F, g.n) & ~prevmask, lvl - 1, (lvl - 1) % 2)
-                            if two_stage and lvl % 2 == 0 and lvl == lo:
-                                load(fmask, lvl - 2, lvl % 2)
+                            if not self.preload:
+                                for mask, src in level_loads(lvl):
+                                    load(mask, src, src % 2)
                             # dependency check: the cross stencil at lvl-1 and (two-stage, even) own cell at lvl-2
                             ys, xs = np.nonzero(fmask)
                             cur = ltag[(lvl - 1) % 2]

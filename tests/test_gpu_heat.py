@@ -44,14 +44,16 @@ def test_c1_config_fp64():
 
 
 def test_fp32_matches_fp32_oracle_and_states_fp64_error():
-    T0 = problems.heat_fourier_modes(128)
+    """FP32 swept vs the FP32 oracle (same operation order), and the stated FP32 error
+    against the FP64 oracle on the C1 initial state (a slowly decaying mode + noise)."""
+    T0 = problems.heat_sine_noise(128)
     sw, r = heat_gpu(T0.astype(np.float32), 0.2, 300, 32, "swept")
     o32 = oracle.heat_run(T0.astype(np.float32), r, 300)
     o64 = oracle.heat_run(T0, r, 300)
     assert rel_err(sw, o32) <= 1e-6
     e64 = rel_err(sw, o64)
     print(f"FP32 GPU vs FP64 oracle (128^2, 300 steps): {e64:.3e}")
-    assert e64 < 1e-4
+    assert e64 < 1e-5
 
 
 def test_zero_steps_is_identity():

@@ -75,3 +75,59 @@ def test_stale_read_is_detected():
     sim = SweptSim(Geom(16, 8, 1, 9), "heat", {"r": 0.2}, store_lag=1)
     with pytest.raises(swept_sim.ProtocolError):
         sim.run(problems.heat_sine_noise(16))
+
+
+@pytest.mark.parametrize("n,b,L", [(1, 8, 30), (1, 16, 37), (1, 6, 20), (2, 16, 30), (2, 12, 25), (2, 8, 13)])
+def test_kernel_ring_rule_matches_rings(n, b, L):
+    """The per-cell rule the phase kernel uses to pick its up-front loads equals the union
+    of the rings Box(F(l), n) minus F(l-1), per level parity, for every shape and cut."""
+    from paper_2105_10332_amd import geometry
+
+    g = Geom(3 * b, b, n, L)
+    W = b + 2 * n
+    C = b // 2 + n
+    for p in range(g.n_phases()):
+        for (wx, wy) in g.shapes(p):
+            lo, hi = g.levels(wx, wy)
+            want = [np.full((W, W), -1), np.full((W, W), -1)]
+            ox = g.centre(wx, 0) - C
+            oy = g.centre(wy, 0) - C
+
+            def mask(f, grow):
+                m = np.zeros((W, W), bool)
+                if f is not None:
+                    m[f[2] - oy - grow:f[3] - oy + grow, f[0] - ox - grow:f[1] - ox + grow] = True
+                return m
+
+            for lvl in range(lo, hi + 1):
+                ring = mask(g.footprint(wx, wy, 0, 0, lvl), n)
+                if lvl > lo:
+                    ring &= ~mask(g.footprint(wx, wy, 0, 0, lvl - 1), 0)
+                assert np.all(want[(lvl - 1) % 2][ring] == -1)
+                want[(lvl - 1) % 2][ring] = lvl - 1
+                if n == 2 and lvl == lo and lvl % 2 == 0:
+                    f = mask(g.footprint(wx, wy, 0, 0, lvl), 0)
+                    want[lvl % 2][f] = lvl - 2
+            got = [np.full((W, W), -1), np.full((W, W), -1)]
+            for ly in range(W):
+                for lx in range(W):
+                    for par, lev in geometry.ring_load_parities(wx, wy, lo, hi, g.h, n, b, lx, ly,
+                                                                two_stage=(n == 2)).items():
+                        got[par][ly, lx] = lev
+            assert np.array_equal(got[0], want[0]) and np.array_equal(got[1], want[1]), (p, wx, wy)
+
+
+@pytest.mark.parametrize("kind,N,b,L", [("heat", 32, 16, 21), ("heat", 18, 6, 10), ("heat", 64, 32, 20),
+                                        ("euler", 24, 12, 14), ("euler", 48, 16, 20)])
+def test_preloaded_protocol(kind, N, b, L):
+    """All of a shape's loads issued before its first level (the kernel's order) is safe."""
+    if kind == "heat":
+        T0 = problems.heat_sine_noise(N)
+        out, _ = SweptSim(Geom(N, b, 1, L), "heat", {"r": 0.2}, preload=True).run(T0)
+        assert np.array_equal(out, oracle.heat_run(T0, 0.2, L))
+    else:
+        Q0 = problems.shu_vortex(N)
+        dx = 10.0 / N
+        dt = oracle.cfl_dt(Q0, dx, dx, 1.4, 0.4)
+        out, _ = SweptSim(Geom(N, b, 2, L), "euler", {"gamma": 1.4, "dt": dt, "dx": dx}, preload=True).run(Q0)
+        assert np.array_equal(out, oracle.euler_run(Q0, dt, dx, dx, 1.4, L // 2))
