@@ -150,6 +150,33 @@ int swept_conserved(swept_ctx* ctx, double* out);
 int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, void* d_work, size_t work_bytes,
                  void* hip_stream, double* dt_out);
 
+/* ---- Adjoint of the swept heat advance (not in the paper) ------------------
+ * For J(T^M) and g = dJ/dT^M, the discrete adjoint of n_steps heat steps
+ * T^{m+1} = A T^m (A = I + r L) gives dJ/dT^0 = (A^T)^n g and
+ * dJ/dalpha = (dt/dx^2) sum_{m<n} <lambda^{m+1}, L T^m>, lambda^m = (A^T)^{n-m} g.
+ * The forward run keeps the flat state at the start of every swept cycle of
+ * h = tile/2 steps (a "tape"); the reverse sweep recomputes each cycle
+ * inside its reverse Octahedra, Bridges and Pyramids in LDS.  Heat only;
+ * the tile must satisfy the LDS limit of the reverse shapes (tile <= 32). */
+
+/* Bytes of tape for an n_steps adjoint: ceil(n_steps/h) checkpoints, six
+ * state-sized scratch buffers, (n_steps mod h) stored levels and the
+ * partial sums.  SWEPT_ENOTSUP for Euler, SWEPT_ESHAPE if the tile is too
+ * large for the adjoint. */
+int swept_tape_bytes(const swept_ctx* ctx, int64_t n_steps, size_t* bytes);
+
+/* swept_advance(n_steps) that also records the checkpoints in d_tape (device
+ * memory of swept_tape_bytes bytes, caller-owned).  Asynchronous. */
+int swept_advance_checkpointed(swept_ctx* ctx, int64_t n_steps, void* d_tape, size_t tape_bytes);
+
+/* Reverse sweep for the run recorded in d_tape (same ctx and n_steps):
+ * d_gTM = dJ/dT^M (state layout and dtype, read-only), d_gT0 = dJ/dT^0
+ * (written), *dJ_dalpha = dJ/dalpha (pairing sums accumulated in double in
+ * a fixed order).  The tape's scratch is overwritten; its checkpoints are
+ * kept.  Does not touch the context's state.  Synchronises the stream. */
+int swept_adjoint(swept_ctx* ctx, int64_t n_steps, void* d_tape, size_t tape_bytes, const void* d_gTM,
+                  void* d_gT0, double* dJ_dalpha);
+
 int swept_destroy(swept_ctx* ctx);
 
 /* Message for the last error on this thread ("" if none). */

@@ -58,6 +58,9 @@ _SIGS = {
     "swept_cfl_dt": [ctypes.POINTER(Problem), _P, ctypes.c_double, _P, ctypes.c_size_t, _P,
                      ctypes.POINTER(ctypes.c_double)],
     "swept_destroy": [_P],
+    "swept_tape_bytes": [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
+    "swept_advance_checkpointed": [_P, ctypes.c_int64, _P, ctypes.c_size_t],
+    "swept_adjoint": [_P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(ctypes.c_double)],
 }
 
 _lib = None

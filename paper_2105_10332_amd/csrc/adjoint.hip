@@ -1,0 +1,277 @@
+// adjoint.hip -- the hand-written adjoint of the swept heat advance.
+//
+// J depends on the final state T^M; given g = dJ/dT^M, the reverse sweep
+// lambda^M = g, lambda^m = A^T lambda^{m+1} gives dJ/dT^0 = lambda^0 and
+// dJ/dr = sum_{m<M} <lambda^{m+1}, L T^m> (T^{m+1} = A T^m, A = I + r L, L the
+// periodic 5-point operator; dJ/dalpha = dJ/dr * dt/dx^2).  A is symmetric,
+// so A^T lambda is the same heat update applied to lambda, and the pairing
+// is evaluated as <L lambda^{m+1}, T^m>, which needs T^m only at the cell
+// where lambda^m is computed.
+//
+// The forward run is cut into cycles of h = b/2 steps with the flat state at
+// each cycle start kept as a checkpoint.  Backward, per cycle:
+//   F0 forward Up-Pyramid of the cycle from the checkpoint, strips -> P;
+//   F1 forward Bridges from P and the checkpoint, strips -> Q (so the
+//      Up-Pyramid's strips in P stay intact);
+//   R0, R1, R2 (this file): lambda over the cycle is itself a swept advance
+//      of h levels in reversed time k = h - j, starting flat, on the other
+//      tiling.  Its k-time Up-Pyramid, Bridges and Down-Pyramid occupy
+//      exactly the footprints of the forward Octahedron 1, the forward
+//      Bridges (X and Y exchanged) and the forward Up-Pyramid plus level 0.
+//      Each reverse workgroup therefore first recomputes the forward T of
+//      its footprint in LDS (R0 from P, Q and the checkpoint, the source of
+//      each input cell chosen by its owner; R1 from P and the checkpoint; R2
+//      from the checkpoint), keeping every level, then runs lambda through
+//      the footprint level by level, pairs each lambda update with T at the
+//      same cell and level, and stores lambda strips for later reverse
+//      shapes with the usual top-two-levels rule.
+// Pairing partial sums are reduced per workgroup in double and written to
+// one slot each; the host sums the slots in a fixed order.
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace swept {
+
+// Forward level of the recompute: F(l) into `cur` (the LDS parity buffer)
+// and into the packed all-levels store `pk` (row-major over the footprint).
+template <typename T>
+__device__ __forceinline__ void heat_level_pack(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ pk,
+                                                int W, const LevelEntry& e, T r)
+{
+    const int fw = e.fw, cells = fw * e.fh;
+    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+        const int q = qdiv(i, e.inv_fw);
+        const int li = (e.y0 + q) * W + (e.x0 + (i - q * fw));
+        const T v = heat_update<T>(prev[li], prev[li + 1], prev[li - 1], prev[li + W], prev[li - W], r);
+        cur[li] = v;
+        pk[i] = v;
+    }
+}
+
+// Reverse level: lambda on F(k) from lambda at k-1 (`prev`), the pairing
+// (L lambda^{k-1}) * T at each cell accumulated in double, and the
+// top-two-levels store of lambda.  T comes from the packed store (row-major
+// over the same footprint) or, for the cycle's level 0, from global memory.
+template <typename T>
+__device__ __forceinline__ double lambda_level(const T* __restrict__ prev, T* __restrict__ cur,
+                                               T* __restrict__ gout, const T* __restrict__ tpk,
+                                               const T* __restrict__ tglob, int W, int C, const LevelEntry& e,
+                                               int hx2, int hy2, int ox, int oy, int N, T r)
+{
+    const int fw = e.fw, cells = fw * e.fh;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < cells; i += blockDim.x) {
+        const int q = qdiv(i, e.inv_fw);
+        const int lx = e.x0 + (i - q * fw), ly = e.y0 + q;
+        const int li = ly * W + lx;
+        const T c = prev[li];
+        const T two_c = c + c;
+        const T dxx = (prev[li + 1] - two_c) + prev[li - 1];
+        const T dyy = (prev[li + W] - two_c) + prev[li - W];
+        const T v = (c + r * dxx) + r * dyy;  // the heat update (scheme.h) with its Laplacian kept
+        cur[li] = v;
+        const int gx = wrapi(ox + lx, N), gy = wrapi(oy + ly, N);
+        const T tv = tpk ? tpk[i] : tglob[(size_t)gy * N + gx];
+        acc += ((double)dxx + (double)dyy) * (double)tv;
+        const int dx = lx - C, dy = ly - C;
+        if (!((dx >= -hx2) && (dx < hx2) && (dy >= -hy2) && (dy < hy2))) gout[(size_t)gy * N + gx] = v;
+    }
+    return acc;
+}
+
+// Sum over the workgroup in a fixed pairwise order (any blockDim).
+__device__ __forceinline__ double block_sum(double v, double* red)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int w = 1; w < nt; w <<= 1) {
+        if ((tid & (2 * w - 1)) == 0 && tid + w < nt) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    return red[0];
+}
+
+// Byte layout of the adjoint workgroup's LDS (shared by host and device).
+struct AdjLds {
+    size_t pk, offs, red, total;
+};
+__host__ __device__ inline AdjLds adjoint_lds_layout(size_t scalar, int tile, int pk_max, int wg)
+{
+    const size_t W = tile + 2;
+    const int h = tile / 2;
+    AdjLds l;
+    l.pk = scalar * 4 * W * W;
+    l.offs = (l.pk + scalar * pk_max + 15) / 16 * 16;
+    l.red = (l.offs + sizeof(int) * (2 * h + 2) + 15) / 16 * 16;
+    l.total = l.red + sizeof(double) * wg;
+    return l;
+}
+
+// One reverse phase (k-time phase 0, 1 or 2) of a full cycle of h levels.
+// LDS: forward parity windows (2 W^2), lambda parity windows (2 W^2), the
+// packed forward levels (pk_max values) and the reduction scratch.
+template <typename T>
+__global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk_max)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int b = a.tile, h = a.h, N = a.N;
+    const int W = b + 2, P = W * W;
+    const size_t NN = (size_t)N * N;
+    const int tiles = a.tiles, t2 = tiles * tiles;
+    const AdjLds lay = adjoint_lds_layout(sizeof(T), b, pk_max, blockDim.x);
+    T* tpar = reinterpret_cast<T*>(smem_raw);
+    T* lpar = tpar + 2 * P;
+    T* pk = reinterpret_cast<T*>(smem_raw + lay.pk);
+    int* offs = reinterpret_cast<int*>(smem_raw + lay.offs);  // packed offset of each forward level
+    double* red = reinterpret_cast<double*>(smem_raw + lay.red);
+
+    // k-time shape of this workgroup (same decode as the forward phases)
+    int kx, ky, inst = blockIdx.x;
+    if ((a.phase & 1) == 0) {
+        kx = ky = a.phase >> 1;
+    } else {
+        const int w = (a.phase + 1) >> 1;
+        const int k = inst >= t2;
+        inst -= k * t2;
+        kx = k ? w - 1 : w;
+        ky = k ? w : w - 1;
+    }
+    const int jx = inst % tiles, jy = inst / tiles;
+    const int fx = 1 - kx, fy = 1 - ky;  // forward shape with the same footprints
+    const int C = b / 2 + 1;
+    // the k-time tiling is the other one (shift), so its centres equal the forward shape's
+    const int cx = jx * b + ((fx & 1) ? 0 : b / 2);
+    const int cy = jy * b + ((fy & 1) ? 0 : b / 2);
+    const int ox = cx - C, oy = cy - C;
+    const T r = (T)a.p[0];
+
+    // ---- forward recompute of levels j = 1..h-1 of shape (fx, fy) ----
+    const int flo = 1, fhi = h - 1;
+    const LevelEntry* ftab;
+    int fkbase;
+    if (fx == fy) {
+        ftab = a.tab;
+        fkbase = fx == 0 ? -h : 0;
+    } else {
+        ftab = a.tab + (fx > fy ? 2 * h : 3 * h);
+        fkbase = 0;
+    }
+    if (threadIdx.x == 0) {
+        int o = 0;
+        for (int j = flo; j <= fhi; ++j) {
+            offs[j] = o;
+            const LevelEntry e = ftab[j - fkbase];
+            o += e.fw * e.fh;
+        }
+    }
+    {
+        const RingSrc<T> src{reinterpret_cast<const T*>(a.buf0), reinterpret_cast<const T*>(a.buf1),
+                             reinterpret_cast<const T*>(a.lvl0), reinterpret_cast<const T*>(a.q0),
+                             reinterpret_cast<const T*>(a.q1), fx == 1 && fy == 1};
+        preload_rings<HeatS, T>(tpar, P, src, W, P, N, NN, ox, oy, fx, fy, flo, fhi, h, C);
+    }
+    __syncthreads();
+    for (int j = flo; j <= fhi; ++j) {
+        const LevelEntry e = ftab[j - fkbase];
+        heat_level_pack<T>(tpar + ((j - 1) & 1) * P, tpar + (j & 1) * P, pk + offs[j], W, e, r);
+        __syncthreads();
+    }
+
+    // ---- reverse sweep in k-time on the same window ----
+    const int kmax = kx > ky ? kx : ky, kmin = kx < ky ? kx : ky;
+    const int klo = max(1, (kmax - 1) * h + 1);
+    const int khi = min(h, (kmin + 1) * h - 1);
+    {
+        const RingSrc<T> src{reinterpret_cast<const T*>(a.lam0), reinterpret_cast<const T*>(a.lam1),
+                             reinterpret_cast<const T*>(a.lam0), nullptr, nullptr, false};
+        preload_rings<HeatS, T>(lpar, P, src, W, P, N, NN, ox, oy, kx, ky, klo, khi, h, C);
+    }
+    const LevelEntry* ktab;
+    int kkbase;
+    if (kx == ky) {
+        ktab = a.tab;
+        kkbase = kx == 0 ? -h : (kx - 1) * h;
+    } else {
+        ktab = a.tab + (kx > ky ? 2 * h : 3 * h);
+        kkbase = (kmax - 1) * h;
+    }
+    __syncthreads();
+    T* l0 = reinterpret_cast<T*>(a.lam0);
+    T* l1 = reinterpret_cast<T*>(a.lam1);
+    double acc = 0.0;
+    for (int k = klo; k <= khi; ++k) {
+        const LevelEntry e = ktab[k - kkbase];
+        const bool has2 = k + 2 <= khi;
+        const int hx2 = has2 ? e.hx2 : 0, hy2 = has2 ? e.hy2 : 0;
+        const int j = h - k;
+        const T* tp = j >= 1 ? pk + offs[j] : nullptr;
+        acc += lambda_level<T>(lpar + ((k - 1) & 1) * P, lpar + (k & 1) * P, (k & 1) ? l1 : l0, tp,
+                               reinterpret_cast<const T*>(a.lvl0), W, C, e, hx2, hy2, ox, oy, N, r);
+        __syncthreads();
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] = tot;
+}
+
+// Remainder steps (a run whose length is not a multiple of h): one adjoint
+// step per launch over the whole grid, lambda_out = A lambda_in, with the
+// pairing against the stored forward level T^m; per-block partial sums.
+template <typename T>
+__global__ void __launch_bounds__(256) adjoint_step_kernel(const T* __restrict__ lin, T* __restrict__ lout,
+                                                           const T* __restrict__ Tm, int N, T r,
+                                                           double* __restrict__ partials)
+{
+    __shared__ double red[256];
+    const size_t NN = (size_t)N * N;
+    double acc = 0.0;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < NN; i += (size_t)gridDim.x * blockDim.x) {
+        const int y = (int)(i / N), x = (int)(i - (size_t)y * N);
+        const size_t row = (size_t)y * N;
+        const T c = lin[i];
+        const T two_c = c + c;
+        const T dxx = (lin[row + wrapi(x + 1, N)] - two_c) + lin[row + wrapi(x - 1, N)];
+        const T dyy = (lin[(size_t)wrapi(y + 1, N) * N + x] - two_c) + lin[(size_t)wrapi(y - 1, N) * N + x];
+        lout[i] = (c + r * dxx) + r * dyy;
+        acc += ((double)dxx + (double)dyy) * (double)Tm[i];
+    }
+    const double tot = block_sum(acc, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = tot;
+}
+
+size_t adjoint_lds(int dtype, int tile, int pk_max, int wg)
+{
+    return adjoint_lds_layout(dtype == 0 ? 8 : 4, tile, pk_max, wg).total;
+}
+
+hipError_t set_adjoint_lds_limit(int dtype, size_t lds)
+{
+    const void* f = dtype == 0 ? (const void*)adjoint_phase_kernel<double> : (const void*)adjoint_phase_kernel<float>;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_adjoint_phase(int dtype, const PhaseArgs& a, int pk_max, int wg, size_t lds, hipStream_t st)
+{
+    const int t2 = a.tiles * a.tiles;
+    const int nblk = (a.phase & 1) ? 2 * t2 : t2;
+    if (dtype == 0)
+        hipLaunchKernelGGL(adjoint_phase_kernel<double>, dim3(nblk), dim3(wg), lds, st, a, pk_max);
+    else
+        hipLaunchKernelGGL(adjoint_phase_kernel<float>, dim3(nblk), dim3(wg), lds, st, a, pk_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const void* Tm, int N, double r,
+                               double* partials, int nblocks, hipStream_t st)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL(adjoint_step_kernel<double>, dim3(nblocks), dim3(256), 0, st, (const double*)lin,
+                           (double*)lout, (const double*)Tm, N, r, partials);
+    else
+        hipLaunchKernelGGL(adjoint_step_kernel<float>, dim3(nblocks), dim3(256), 0, st, (const float*)lin,
+                           (float*)lout, (const float*)Tm, N, (float)r, partials);
+    return hipGetLastError();
+}
+
+}  // namespace swept

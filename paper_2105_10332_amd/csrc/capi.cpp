@@ -43,10 +43,15 @@ struct Derived {
     double r, dx, dy;
 };
 
+// LDS of one swept workgroup: heat keeps two level-parity windows; Euler
+// also a pressure plane and a face-flux buffer (kernels.hip, euler_level).
 size_t phase_lds(int nvar, int n, int tile, size_t scalar)
 {
-    const size_t W = (size_t)tile + 2 * n;
-    return 2 * nvar * W * W * scalar;
+    if (nvar == 1) {
+        const size_t W = (size_t)tile + 2 * n;
+        return 2 * W * W * scalar;
+    }
+    return swept::euler_phase_lds(scalar == 8 ? 0 : 1, tile);
 }
 
 bool tile_ok(int N, int tile, int n, int nvar, size_t scalar)
@@ -124,6 +129,36 @@ size_t workspace_for(const Derived& d)
            align_up(table_bytes(d));
 }
 
+// ---- adjoint tape (heat): checkpoints, scratch pairs, remainder stash, partial sums
+struct TapePlan {
+    int64_t cycles, rem;  // n_steps = cycles*h + rem
+    int64_t nck;          // checkpoints: one per cycle start, plus the remainder's start
+    int pk_max;           // packed forward levels per reverse workgroup
+    int std_blocks;       // blocks of the remainder's one-step adjoint kernel
+    size_t ck_off, pairs_off, stash_off, part_off, total;
+    int64_t nparts;
+};
+
+constexpr int kStdAdjBlocks = 1024;
+
+int tape_plan(const Derived& d, int nx, int64_t n_steps, TapePlan* t)
+{
+    const int h = d.h, tiles = nx / d.tile;
+    t->cycles = n_steps / h;
+    t->rem = n_steps % h;
+    t->nck = t->cycles + (t->rem > 0 ? 1 : 0);
+    t->pk_max = 4 * (h - 1) * h * (2 * h - 1) / 6;  // sum_{j<h} (2j)^2: the largest recomputed footprint
+    t->std_blocks = kStdAdjBlocks;
+    const size_t S = align_up(d.state_bytes);
+    t->ck_off = 0;
+    t->pairs_off = t->ck_off + S * (size_t)t->nck;
+    t->stash_off = t->pairs_off + 6 * S;  // P0 P1 Q0 Q1 L0 L1
+    t->part_off = t->stash_off + S * (size_t)t->rem;
+    t->nparts = t->cycles * 4 * (int64_t)tiles * tiles + t->rem * kStdAdjBlocks;
+    t->total = t->part_off + align_up(sizeof(double) * (size_t)(t->nparts + 1));
+    return SWEPT_OK;
+}
+
 int half_width_host(int t, int h, int n)
 {
     if (t < 1 || t > 2 * h - 1) return 0;
@@ -141,12 +176,14 @@ void build_level_table(const Derived& d, swept::LevelEntry* tab)
         e.y0 = C - hy;
         e.fw = 2 * hx;
         e.fh = 2 * hy;
-        const int cells = e.fw * e.fh;
-        e.R = cells <= d.wg ? 1 : (cells + d.wg - 1) / d.wg;
+        e.pw = hx;  // fw is even: pairs of columns
+        const int pairs = e.pw * e.fh;
+        e.R = pairs <= d.wg ? 1 : (pairs + d.wg - 1) / d.wg;
         e.spc = (e.fh + e.R - 1) / e.R;
         e.hx2 = hx2;
         e.hy2 = hy2;
         e.inv_fw = e.fw > 0 ? 1.0f / (float)e.fw : 0.0f;
+        e.inv_pw = e.pw > 0 ? 1.0f / (float)e.pw : 0.0f;
     };
     for (int t = 1; t <= 2 * h - 1; ++t) {  // Octahedron
         const int hw = half_width_host(t, h, n), hw2 = half_width_host(t + 2, h, n);
@@ -176,6 +213,7 @@ struct swept_ctx {
     double c[5];  // scheme constants (see PhaseArgs)
     int std_ts;
     swept::LevelEntry* tab_dev;  // level table inside the workspace
+    size_t adj_lds;              // LDS of an adjoint workgroup (0: adjoint unavailable)
 };
 
 extern "C" {
@@ -240,6 +278,19 @@ int swept_init(swept_ctx** ctx, const swept_problem* prob, const swept_tuning* t
         delete c;
         return hip_fail(e, "hipFuncSetAttribute");
     }
+    c->adj_lds = 0;
+    if (prob->kind == SWEPT_HEAT) {
+        const int h = d.h, pk_max = 4 * (h - 1) * h * (2 * h - 1) / 6;
+        const size_t lds = swept::adjoint_lds(prob->dtype, d.tile, pk_max, d.wg);
+        if (lds <= kLdsMax) {
+            c->adj_lds = lds;
+            e = swept::set_adjoint_lds_limit(prob->dtype, kLdsMax);
+            if (e != hipSuccess) {
+                delete c;
+                return hip_fail(e, "hipFuncSetAttribute");
+            }
+        }
+    }
     {
         const int ne = swept::level_table_entries(d.h);
         swept::LevelEntry* host = new (std::nothrow) swept::LevelEntry[ne];
@@ -284,18 +335,12 @@ int swept_set_stream(swept_ctx* c, void* hip_stream)
     return SWEPT_OK;
 }
 
-int swept_advance(swept_ctx* c, int64_t n_steps)
+static swept::PhaseArgs phase_args(const swept_ctx* c, int L)
 {
-    if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
-    if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
-    if (n_steps == 0) return SWEPT_OK;
-    const int64_t L64 = n_steps * c->d.lps;
-    if (L64 > (int64_t)1 << 30) return fail(SWEPT_EINVAL, "n_steps too large");
-    const int L = (int)L64;
-    const int W = (L + c->d.h - 1) / c->d.h;
-    swept::PhaseArgs a;
-    a.buf0 = c->state;
-    a.buf1 = c->buf1;
+    swept::PhaseArgs a{};
+    a.buf0 = a.out0 = c->state;
+    a.buf1 = a.out1 = c->buf1;
+    a.lvl0 = c->state;
     a.N = c->prob.nx;
     a.tile = c->d.tile;
     a.h = c->d.h;
@@ -303,6 +348,18 @@ int swept_advance(swept_ctx* c, int64_t n_steps)
     a.L = L;
     a.tab = c->tab_dev;
     for (int k = 0; k < 5; ++k) a.p[k] = c->c[k];
+    return a;
+}
+
+// Swept advance of n_steps on the context's state, flat to flat.
+static int advance_impl(swept_ctx* c, int64_t n_steps)
+{
+    if (n_steps == 0) return SWEPT_OK;
+    const int64_t L64 = n_steps * c->d.lps;
+    if (L64 > (int64_t)1 << 30) return fail(SWEPT_EINVAL, "n_steps too large");
+    const int L = (int)L64;
+    const int W = (L + c->d.h - 1) / c->d.h;
+    swept::PhaseArgs a = phase_args(c, L);
     for (int ph = 0; ph <= 2 * W; ++ph) {
         a.phase = ph;
         hipError_t e = swept::launch_phase(c->prob.kind, c->prob.dtype, a, c->d.wg, c->d.lds_bytes, c->stream);
@@ -312,6 +369,138 @@ int swept_advance(swept_ctx* c, int64_t n_steps)
         hipError_t e = hipMemcpyAsync(c->state, c->buf1, c->d.state_bytes, hipMemcpyDeviceToDevice, c->stream);
         if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
     }
+    return SWEPT_OK;
+}
+
+int swept_advance(swept_ctx* c, int64_t n_steps)
+{
+    if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
+    if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
+    return advance_impl(c, n_steps);
+}
+
+static int tape_check(const swept_ctx* c, int64_t n_steps, TapePlan* t)
+{
+    if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
+    if (c->prob.kind != SWEPT_HEAT) return fail(SWEPT_ENOTSUP, "the adjoint is implemented for heat only");
+    if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
+    if (c->adj_lds == 0)
+        return fail(SWEPT_ESHAPE, "tile %d too large for the adjoint's LDS (all levels of a shape are kept)",
+                    c->d.tile);
+    return tape_plan(c->d, c->prob.nx, n_steps, t);
+}
+
+int swept_tape_bytes(const swept_ctx* c, int64_t n_steps, size_t* bytes)
+{
+    if (!bytes) return fail(SWEPT_EINVAL, "bytes is NULL");
+    TapePlan t;
+    const int rc = tape_check(c, n_steps, &t);
+    if (rc) return rc;
+    *bytes = t.total;
+    return SWEPT_OK;
+}
+
+int swept_advance_checkpointed(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes)
+{
+    TapePlan t;
+    int rc = tape_check(c, n_steps, &t);
+    if (rc) return rc;
+    if (!d_tape) return fail(SWEPT_EINVAL, "tape is NULL");
+    if (tape_bytes < t.total) return fail(SWEPT_EWORKSPACE, "tape %zu bytes < %zu needed", tape_bytes, t.total);
+    char* tape = static_cast<char*>(d_tape);
+    const size_t S = align_up(c->d.state_bytes);
+    for (int64_t k = 0; k < t.nck; ++k) {
+        hipError_t e = hipMemcpyAsync(tape + t.ck_off + S * k, c->state, c->d.state_bytes, hipMemcpyDeviceToDevice,
+                                      c->stream);
+        if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+        rc = advance_impl(c, k < t.cycles ? c->d.h : t.rem);
+        if (rc) return rc;
+    }
+    return SWEPT_OK;
+}
+
+int swept_adjoint(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes, const void* d_gTM, void* d_gT0,
+                  double* dJ_dalpha)
+{
+    TapePlan t;
+    int rc = tape_check(c, n_steps, &t);
+    if (rc) return rc;
+    if (!d_tape || !d_gTM || !d_gT0 || !dJ_dalpha) return fail(SWEPT_EINVAL, "NULL argument");
+    if (tape_bytes < t.total) return fail(SWEPT_EWORKSPACE, "tape %zu bytes < %zu needed", tape_bytes, t.total);
+    char* tape = static_cast<char*>(d_tape);
+    const size_t S = align_up(c->d.state_bytes), SB = c->d.state_bytes;
+    auto ck = [&](int64_t k) { return static_cast<void*>(tape + t.ck_off + S * k); };
+    void* P0 = tape + t.pairs_off;
+    void* P1 = tape + t.pairs_off + S;
+    void* Q0 = tape + t.pairs_off + 2 * S;
+    void* Q1 = tape + t.pairs_off + 3 * S;
+    void* La = tape + t.pairs_off + 4 * S;  // lambda at the start of the next reverse step / cycle
+    void* Lb = tape + t.pairs_off + 5 * S;
+    double* parts = reinterpret_cast<double*>(tape + t.part_off);
+    const int N = c->prob.nx, tiles = N / c->d.tile, t2 = tiles * tiles, h = c->d.h;
+    hipStream_t st = c->stream;
+    hipError_t e = hipMemcpyAsync(La, d_gTM, SB, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint init copy");
+    int64_t pslot = 0;
+    if (t.rem > 0) {  // the last rem steps: forward levels into the stash, then one adjoint step per level
+        char* stash = tape + t.stash_off;
+        e = hipMemcpyAsync(stash, ck(t.cycles), SB, hipMemcpyDeviceToDevice, st);
+        for (int64_t m = 1; m < t.rem && e == hipSuccess; ++m)
+            e = swept::launch_heat_standard(c->prob.dtype, stash + S * (m - 1), stash + S * m, N, c->d.r, st);
+        for (int64_t m = t.rem - 1; m >= 0 && e == hipSuccess; --m) {
+            e = swept::launch_adjoint_step(c->prob.dtype, La, Lb, stash + S * m, N, c->d.r, parts + pslot,
+                                           t.std_blocks, st);
+            pslot += t.std_blocks;
+            void* tmp = La;
+            La = Lb;
+            Lb = tmp;
+        }
+        if (e != hipSuccess) return hip_fail(e, "adjoint remainder");
+    }
+    for (int64_t cyc = t.cycles - 1; cyc >= 0; --cyc) {
+        // forward Up-Pyramid -> P, forward Bridges -> Q (level 0 from the checkpoint)
+        swept::PhaseArgs f = phase_args(c, h);
+        f.buf0 = f.out0 = P0;
+        f.buf1 = f.out1 = P1;
+        f.lvl0 = ck(cyc);
+        f.phase = 0;
+        e = swept::launch_phase(SWEPT_HEAT, c->prob.dtype, f, c->d.wg, c->d.lds_bytes, st);
+        if (e != hipSuccess) return hip_fail(e, "adjoint forward phase");
+        f.out0 = Q0;
+        f.out1 = Q1;
+        f.phase = 1;
+        e = swept::launch_phase(SWEPT_HEAT, c->prob.dtype, f, c->d.wg, c->d.lds_bytes, st);
+        if (e != hipSuccess) return hip_fail(e, "adjoint forward phase");
+        // reverse phases on the other tiling
+        swept::PhaseArgs a = phase_args(c, h);
+        a.buf0 = P0;
+        a.buf1 = P1;
+        a.q0 = Q0;
+        a.q1 = Q1;
+        a.lvl0 = ck(cyc);
+        a.lam0 = La;
+        a.lam1 = Lb;
+        a.shift = 1;
+        for (int ph = 0; ph <= 2; ++ph) {
+            a.phase = ph;
+            a.partials = parts + pslot;
+            pslot += (ph & 1) ? 2 * t2 : t2;
+            e = swept::launch_adjoint_phase(c->prob.dtype, a, t.pk_max, c->d.wg, c->adj_lds, st);
+            if (e != hipSuccess) return hip_fail(e, "adjoint phase launch");
+        }
+        if (h & 1) {  // lambda of the cycle start lives in the odd buffer
+            void* tmp = La;
+            La = Lb;
+            Lb = tmp;
+        }
+    }
+    e = hipMemcpyAsync(d_gT0, La, SB, hipMemcpyDeviceToDevice, st);
+    if (e == hipSuccess) e = swept::launch_combine(parts, (int)pslot, parts + t.nparts, st);
+    double dJdr = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&dJdr, parts + t.nparts, sizeof(double), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint finish");
+    *dJ_dalpha = dJdr * c->prob.dt / (c->d.dx * c->d.dx);
     return SWEPT_OK;
 }
 

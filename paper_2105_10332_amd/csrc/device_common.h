@@ -1,0 +1,330 @@
+// device_common.h -- device helpers shared by the swept phase kernels and
+// the adjoint kernels: exact small quotients, periodic wrap, the 1D diamond
+// geometry, the up-front ring load, and the per-level heat and Euler updates
+// of a window in LDS.  Memory protocol: see kernels.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "launch.h"
+#include "scheme.h"
+
+namespace swept {
+
+// Exact quotient i / d for 0 <= i < 2^13 and 1 <= d <= 160 from a float
+// reciprocal: the rounding error of (i + 0.5) * inv stays far below the
+// 0.5/d distance of (i + 0.5)/d to an integer.
+__device__ __forceinline__ int qdiv(int i, float inv) { return (int)(((float)i + 0.5f) * inv); }
+
+__device__ __forceinline__ int wrapi(int g, int N)
+{
+    g += (g < 0) ? N : 0;
+    g -= (g >= N) ? N : 0;
+    return g;
+}
+
+struct HeatS {
+    static constexpr int NVAR = 1, R = 1, TWO_STAGE = 0, MAXWG = 1024;
+};
+struct EulerS {  // register-heavy per-cell update: at most 256 threads so nothing spills
+    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 256;
+};
+
+__device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
+{
+    const int t = lvl - (w - 1) * h;
+    if (lvl < 1 || t < 1 || t > 2 * h - 1) return 0;
+    return n * (t < 2 * h - t ? t : 2 * h - t);
+}
+
+// Which level-parity buffers the up-front load fills at local cell (lx, ly):
+// bit p set <=> the cell lies in a ring(l) = Box(F(l), n) minus F(l-1) with
+// (l-1)%2 == p.  With t = l - (w-1)h and a the cell's distance index from
+// the centre along a growing axis (inside <=> a < hw), ring(t) holds
+// (t-1)n <= a < (t+1)n, so the candidates t = a/n and a/n + 1 have opposite
+// parities:
+//   Octahedron w >= 1: a = max(ax, ay), t <= min(h, tmax);
+//   Bridge: a along the growing axis, t <= min(h-1, tmax), and the shrinking
+//     axis must satisfy s < (h-t+1)n;
+//   Up-Pyramid (w = 0): only its first level, the tile at level 0;
+// tmax = hi - (w-1)h (the cut at the final level).  A two-stage scheme whose
+// first level is even also needs F(lo) at level lo-2 (buffer lo%2).
+// Extra bits: RING_LEVEL0 -- the parity-0 value is level 0 (the initial
+// state, which may live in its own buffer); RING_Q0/RING_Q1 (only when
+// owner_q is set, for Octahedron 1 of a flat-to-flat cycle) -- the value
+// was produced by a Bridge rather than the Up-Pyramid (the adjoint keeps
+// the two in separate buffers): at level l-1 >= 1 a ring cell belongs to
+// the Up-Pyramid iff it is outside diamond 1 on both axes.
+constexpr int RING_LEVEL0 = 4, RING_Q0 = 8, RING_Q1 = 16;
+
+template <int R, int TWO_STAGE>
+__device__ __forceinline__ int ring_parities(int wx, int wy, int lo, int hi, int h, int b, int C, int lx, int ly,
+                                             bool owner_q = false)
+{
+    const int ax = lx >= C ? lx - C : C - 1 - lx;
+    const int ay = ly >= C ? ly - C : C - 1 - ly;
+    const int wmax = wx > wy ? wx : wy;
+    if (wmax == 0) return (ax < b / 2 && ay < b / 2) ? (1 | RING_LEVEL0) : 0;
+    const int base = (wmax - 1) * h;
+    const int tmax = hi - base;
+    int a, s, tcap;
+    if (wx == wy) {
+        a = ax > ay ? ax : ay;
+        s = -1;  // no shrinking axis
+        tcap = h < tmax ? h : tmax;
+    } else {
+        a = wx > wy ? ax : ay;
+        s = wx > wy ? ay : ax;
+        tcap = (h - 1) < tmax ? (h - 1) : tmax;
+    }
+    const int t1 = a / R;
+    int m = 0;
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int t = t1 + k;
+        if (t >= 1 && t <= tcap && s < (h - t + 1) * R) {
+            const int lev = base + t - 1;
+            const int p = lev & 1;
+            m |= 1 << p;
+            if (lev == 0) m |= RING_LEVEL0;
+            if (owner_q && lev > 0) {
+                const int hw = half_width(wx, lev, h, R);
+                if ((ax < hw) || (ay < hw)) m |= p ? RING_Q1 : RING_Q0;
+            }
+        }
+    }
+    if (TWO_STAGE && (lo & 1) == 0 && ax < half_width(wx, lo, h, R) && ay < half_width(wy, lo, h, R))
+        m |= 1 << (lo & 1);
+    return m;
+}
+
+// Sources of the up-front load: level-parity buffers g0/g1, the level-0
+// state (normally g0 itself) and, for the adjoint, the Bridges' buffers.
+template <typename T>
+struct RingSrc {
+    const T* g0;
+    const T* g1;
+    const T* lvl0;
+    const T* q0;
+    const T* q1;
+    bool owner_q;
+};
+
+// Up-front load of every ring of the shape: a strided pass over the window,
+// KB cells per thread per batch with all their loads issued before any LDS
+// write, so the batch costs one memory latency.
+template <class S, typename T>
+__device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>& src, int W, int P, int N, size_t NN,
+                                              int ox, int oy, int wx, int wy, int lo, int hi, int h, int C)
+{
+    constexpr int NVAR = S::NVAR, KB = 4;
+    const int cnt = W * W;
+    const float invW = 1.0f / (float)W;
+    for (int base = 0; base < cnt; base += KB * (int)blockDim.x) {
+        T v[KB][2][NVAR];
+        int li[KB], pm[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
+            pm[k] = 0;
+            li[k] = i;
+            if (i < cnt) {
+                const int ly = qdiv(i, invW), lx = i - ly * W;
+                pm[k] = ring_parities<S::R, S::TWO_STAGE>(wx, wy, lo, hi, h, W - 2 * S::R, C, lx, ly, src.owner_q);
+                if (pm[k] & 3) {
+                    const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
+                    if (pm[k] & 1) {
+                        const T* g = (pm[k] & RING_LEVEL0) ? src.lvl0 : ((pm[k] & RING_Q0) ? src.q0 : src.g0);
+#pragma unroll
+                        for (int c = 0; c < NVAR; ++c) v[k][0][c] = g[c * NN + gi];
+                    }
+                    if (pm[k] & 2) {
+                        const T* g = (pm[k] & RING_Q1) ? src.q1 : src.g1;
+#pragma unroll
+                        for (int c = 0; c < NVAR; ++c) v[k][1][c] = g[c * NN + gi];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+                if (pm[k] & (1 << p))
+#pragma unroll
+                    for (int c = 0; c < NVAR; ++c) lds[p * BUF + c * P + li[k]] = v[k][p][c];
+    }
+}
+
+template <typename T, class Store>
+__device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, T* __restrict__ pbuf,
+                                            T* __restrict__ fbuf, int FS, int W, int P, int x0, int y0, int fw, int fh,
+                                            bool second_stage, T gamma, T cx, T cy, const Store& store)
+{
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    const T gm1 = gamma - T(1);
+    {  // A: pressures on [x0-2, x0+fw+2) x [y0-2, y0+fh+2)
+        const int bw = fw + 4, cnt = bw * (fh + 4);
+        const float inv = 1.0f / (float)bw;
+        for (int i = tid; i < cnt; i += nthr) {
+            const int q = qdiv(i, inv);
+            const int li = (y0 - 2 + q) * W + (x0 - 2 + (i - q * bw));
+            T s4[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) s4[c] = prev[c * P + li];
+            pbuf[li] = pressure(s4, gm1);
+        }
+    }
+    __syncthreads();
+    {  // B1: x faces between cells x0-1+k and x0+k, k = 0..fw, rows y0..y0+fh-1
+        const int nf = fw + 1, cnt = nf * fh;
+        const float inv = 1.0f / (float)nf;
+        for (int i = tid; i < cnt; i += nthr) {
+            const int q = qdiv(i, inv);
+            const int k = i - q * nf;
+            const int lb = (y0 + q) * W + (x0 - 1 + k);
+            T qa[4], qb[4], qc[4], qd[4], f[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                qa[c] = prev[c * P + lb - 1];
+                qb[c] = prev[c * P + lb];
+                qc[c] = prev[c * P + lb + 1];
+                qd[c] = prev[c * P + lb + 2];
+            }
+            face_flux<T, 1>(qa, qb, qc, qd, pbuf[lb - 1], pbuf[lb], pbuf[lb + 1], pbuf[lb + 2], gamma, f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fbuf[c * FS + i] = f[c];
+        }
+    }
+    __syncthreads();
+    const int cells = fw * fh;
+    const float inv_fw = 1.0f / (float)fw;
+    {  // C1: x update
+        const int nf = fw + 1;
+        for (int i = tid; i < cells; i += nthr) {
+            const int q = qdiv(i, inv_fw);
+            const int k = i - q * fw;
+            const int li = (y0 + q) * W + (x0 + k);
+            const int fi = q * nf + k;  // face i-1/2; face i+1/2 is fi + 1
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const T base = second_stage ? cur[c * P + li] : prev[c * P + li];
+                const T dF = fbuf[c * FS + fi + 1] - fbuf[c * FS + fi];
+                cur[c * P + li] = base - cx * dF;
+            }
+        }
+    }
+    __syncthreads();
+    {  // B2: y faces between rows y0-1+k and y0+k, k = 0..fh, columns x0..x0+fw-1
+        const int cnt = fw * (fh + 1);
+        for (int i = tid; i < cnt; i += nthr) {
+            const int k = qdiv(i, inv_fw);
+            const int xo = i - k * fw;
+            const int lb = (y0 - 1 + k) * W + (x0 + xo);
+            T qa[4], qb[4], qc[4], qd[4], f[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                qa[c] = prev[c * P + lb - W];
+                qb[c] = prev[c * P + lb];
+                qc[c] = prev[c * P + lb + W];
+                qd[c] = prev[c * P + lb + 2 * W];
+            }
+            face_flux<T, 2>(qa, qb, qc, qd, pbuf[lb - W], pbuf[lb], pbuf[lb + W], pbuf[lb + 2 * W], gamma, f);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fbuf[c * FS + i] = f[c];
+        }
+    }
+    __syncthreads();
+    {  // C2: y update, then hand the finished cell to the store policy
+        for (int i = tid; i < cells; i += nthr) {
+            const int q = qdiv(i, inv_fw);
+            const int k = i - q * fw;
+            const int lx = x0 + k, ly = y0 + q;
+            const int li = ly * W + lx;
+            const int fi = q * fw + k;  // face j-1/2; face j+1/2 is fi + fw
+            T out[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const T dG = fbuf[c * FS + fi + fw] - fbuf[c * FS + fi];
+                out[c] = cur[c * P + li] - cy * dG;
+                cur[c * P + li] = out[c];
+            }
+            store(lx, ly, out);
+        }
+    }
+}
+
+// Swept store policy: cells outside F(l+2) go to the level's global buffer.
+template <typename T, int NVAR>
+struct SweptStore {
+    T* g;
+    size_t NN;
+    int N, ox, oy, C, hx2, hy2;
+    __device__ __forceinline__ void operator()(int lx, int ly, const T* v) const
+    {
+        const int dx = lx - C, dy = ly - C;  // in F(l+2) <=> -hw2 <= d < hw2
+        if ((dx >= -hx2) && (dx < hx2) && (dy >= -hy2) && (dy < hy2)) return;
+        const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
+#pragma unroll
+        for (int c = 0; c < NVAR; ++c) g[c * NN + gi] = v[c];
+    }
+};
+
+struct NoStore {
+    template <typename V>
+    __device__ __forceinline__ void operator()(int, int, const V*) const {}
+};
+
+// LDS layout of an Euler window: two level-parity state buffers (4 planes of
+// W*W), one pressure plane, one face buffer of 4 planes of FS values.
+__host__ __device__ inline size_t euler_lds_values(int W, int FS) { return (size_t)8 * W * W + W * W + 4 * FS; }
+
+// One heat level on the footprint [x0, x0+fw) x [y0, y0+fh) of the window.
+// Each thread takes two adjacent columns and walks a vertical strip of R
+// rows of them (R from the level table, so the footprint spreads over the
+// whole workgroup), keeping the vertical neighbours in registers: per row
+// two paired LDS reads (the next row of both columns; the outer left/right
+// neighbours) and one paired LDS write for two cell-updates.  Cells outside
+// F(l+2) (half-widths hx2, hy2) also go to the level's global buffer.
+template <typename T>
+__device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ gout,
+                                           int W, int C, const LevelEntry& e, int hx2, int hy2, int ox, int oy,
+                                           int N, T r)
+{
+    const int pw = e.pw, nthr = blockDim.x;
+    const int NN = N * N;
+    const int ylo2 = C - hy2, yhi2 = C + hy2;  // rows inside F(l+2)
+    for (int t = threadIdx.x; t < pw * e.spc; t += nthr) {
+        const int sidx = qdiv(t, e.inv_pw);
+        const int x = e.x0 + 2 * (t - sidx * pw);
+        const int ys = e.y0 + sidx * e.R;
+        const int ye = min(ys + e.R, e.y0 + e.fh);
+        const bool xk0 = (x - C >= -hx2) && (x - C < hx2);
+        const bool xk1 = (x + 1 - C >= -hx2) && (x + 1 - C < hx2);
+        const int gx0 = wrapi(ox + x, N), gx1 = wrapi(ox + x + 1, N);
+        int grow = wrapi(oy + ys, N) * N;
+        int li = ys * W + x;
+        T up0 = prev[li - W], up1 = prev[li - W + 1];
+        T c0 = prev[li], c1 = prev[li + 1];
+        for (int y = ys; y < ye; ++y) {
+            const T dn0 = prev[li + W], dn1 = prev[li + W + 1];
+            const T lft = prev[li - 1], rgt = prev[li + 2];
+            const T v0 = heat_update<T>(c0, c1, lft, dn0, up0, r);
+            const T v1 = heat_update<T>(c1, rgt, c0, dn1, up1, r);
+            cur[li] = v0;
+            cur[li + 1] = v1;
+            const bool yk = (y >= ylo2) && (y < yhi2);
+            if (!(yk && xk0)) gout[grow + gx0] = v0;
+            if (!(yk && xk1)) gout[grow + gx1] = v1;
+            up0 = c0;
+            up1 = c1;
+            c0 = dn0;
+            c1 = dn1;
+            li += W;
+            grow += N;
+            grow = grow >= NN ? grow - NN : grow;
+        }
+    }
+}
+
+}  // namespace swept

@@ -24,197 +24,9 @@
 //      cell's top two levels, exactly the values later shapes read.
 #include <hip/hip_runtime.h>
 
-#include "launch.h"
-#include "scheme.h"
+#include "device_common.h"
 
 namespace swept {
-
-// Exact quotient i / d for 0 <= i < 2^13 and 1 <= d <= 160 from a float
-// reciprocal: the rounding error of (i + 0.5) * inv stays far below the
-// 0.5/d distance of (i + 0.5)/d to an integer.
-__device__ __forceinline__ int qdiv(int i, float inv) { return (int)(((float)i + 0.5f) * inv); }
-
-__device__ __forceinline__ int wrapi(int g, int N)
-{
-    g += (g < 0) ? N : 0;
-    g -= (g >= N) ? N : 0;
-    return g;
-}
-
-struct HeatS {
-    static constexpr int NVAR = 1, R = 1, TWO_STAGE = 0, MAXWG = 1024;
-};
-struct EulerS {  // register-heavy per-cell update: at most 256 threads so nothing spills
-    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 256;
-};
-
-__device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
-{
-    const int t = lvl - (w - 1) * h;
-    if (lvl < 1 || t < 1 || t > 2 * h - 1) return 0;
-    return n * (t < 2 * h - t ? t : 2 * h - t);
-}
-
-// Which level-parity buffers the up-front load fills at local cell (lx, ly):
-// bit p set <=> the cell lies in a ring(l) = Box(F(l), n) minus F(l-1) with
-// (l-1)%2 == p.  With t = l - (w-1)h and a the cell's distance index from
-// the centre along a growing axis (inside <=> a < hw), ring(t) holds
-// (t-1)n <= a < (t+1)n, so the candidates t = a/n and a/n + 1 have opposite
-// parities:
-//   Octahedron w >= 1: a = max(ax, ay), t <= min(h, tmax);
-//   Bridge: a along the growing axis, t <= min(h-1, tmax), and the shrinking
-//     axis must satisfy s < (h-t+1)n;
-//   Up-Pyramid (w = 0): only its first level, the tile at level 0;
-// tmax = hi - (w-1)h (the cut at the final level).  A two-stage scheme whose
-// first level is even also needs F(lo) at level lo-2 (buffer lo%2).
-template <int R, int TWO_STAGE>
-__device__ __forceinline__ int ring_parities(int wx, int wy, int lo, int hi, int h, int b, int C, int lx, int ly)
-{
-    const int ax = lx >= C ? lx - C : C - 1 - lx;
-    const int ay = ly >= C ? ly - C : C - 1 - ly;
-    const int wmax = wx > wy ? wx : wy;
-    if (wmax == 0) return (ax < b / 2 && ay < b / 2) ? 1 : 0;
-    const int base = (wmax - 1) * h;
-    const int tmax = hi - base;
-    int a, s, tcap;
-    if (wx == wy) {
-        a = ax > ay ? ax : ay;
-        s = -1;  // no shrinking axis
-        tcap = h < tmax ? h : tmax;
-    } else {
-        a = wx > wy ? ax : ay;
-        s = wx > wy ? ay : ax;
-        tcap = (h - 1) < tmax ? (h - 1) : tmax;
-    }
-    const int t1 = a / R;
-    int m = 0;
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-        const int t = t1 + k;
-        if (t >= 1 && t <= tcap && s < (h - t + 1) * R) m |= 1 << ((base + t - 1) & 1);
-    }
-    if (TWO_STAGE && (lo & 1) == 0 && ax < half_width(wx, lo, h, R) && ay < half_width(wy, lo, h, R))
-        m |= 1 << (lo & 1);
-    return m;
-}
-
-// Up-front load of every ring of the shape: a strided pass over the window,
-// KB cells per thread per batch with all their loads issued before any LDS
-// write, so the batch costs one memory latency.
-template <class S, typename T>
-__device__ __forceinline__ void preload_rings(T* lds, int BUF, const T* g0, const T* g1, int W, int P, int N,
-                                              size_t NN, int ox, int oy, int wx, int wy, int lo, int hi, int h, int C)
-{
-    constexpr int NVAR = S::NVAR, KB = 4;
-    const int cnt = W * W;
-    const float invW = 1.0f / (float)W;
-    for (int base = 0; base < cnt; base += KB * (int)blockDim.x) {
-        T v[KB][2][NVAR];
-        int li[KB], pm[KB];
-#pragma unroll
-        for (int k = 0; k < KB; ++k) {
-            const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
-            pm[k] = 0;
-            li[k] = i;
-            if (i < cnt) {
-                const int ly = qdiv(i, invW), lx = i - ly * W;
-                pm[k] = ring_parities<S::R, S::TWO_STAGE>(wx, wy, lo, hi, h, W - 2 * S::R, C, lx, ly);
-                if (pm[k]) {
-                    const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
-                    if (pm[k] & 1)
-#pragma unroll
-                        for (int c = 0; c < NVAR; ++c) v[k][0][c] = g0[c * NN + gi];
-                    if (pm[k] & 2)
-#pragma unroll
-                        for (int c = 0; c < NVAR; ++c) v[k][1][c] = g1[c * NN + gi];
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < KB; ++k)
-#pragma unroll
-            for (int p = 0; p < 2; ++p)
-                if (pm[k] & (1 << p))
-#pragma unroll
-                    for (int c = 0; c < NVAR; ++c) lds[p * BUF + c * P + li[k]] = v[k][p][c];
-    }
-}
-
-template <class S, typename T>
-__device__ __forceinline__ void cell_update(const T* prev, const T* cur, int li, int W, int P, int lvl,
-                                            const PhaseArgs& a, T out[S::NVAR]);
-
-template <>
-__device__ __forceinline__ void cell_update<HeatS, double>(const double* prev, const double*, int li, int W, int,
-                                                           int, const PhaseArgs& a, double out[1])
-{
-    out[0] = heat_update<double>(prev[li], prev[li + 1], prev[li - 1], prev[li + W], prev[li - W], a.p[0]);
-}
-template <>
-__device__ __forceinline__ void cell_update<HeatS, float>(const float* prev, const float*, int li, int W, int, int,
-                                                          const PhaseArgs& a, float out[1])
-{
-    out[0] = heat_update<float>(prev[li], prev[li + 1], prev[li - 1], prev[li + W], prev[li - W], (float)a.p[0]);
-}
-template <typename T>
-__device__ __forceinline__ void euler_update(const T* prev, const T* cur, int li, int W, int P, int lvl,
-                                             const PhaseArgs& a, T out[4])
-{
-    const T gamma = (T)a.p[0];
-    if (lvl & 1)  // Q* = Q^m - dt/2 ...: base and fluxes from level l-1
-        euler_cell<T>(prev, P, W, li, prev, P, li, gamma, (T)a.p[1], (T)a.p[2], out);
-    else  // Q^{m+1} = Q^m - dt ...(Q*): base is the cell's own level l-2 value in `cur`
-        euler_cell<T>(prev, P, W, li, cur, P, li, gamma, (T)a.p[3], (T)a.p[4], out);
-}
-template <>
-__device__ __forceinline__ void cell_update<EulerS, double>(const double* prev, const double* cur, int li, int W,
-                                                            int P, int lvl, const PhaseArgs& a, double out[4])
-{
-    euler_update<double>(prev, cur, li, W, P, lvl, a, out);
-}
-template <>
-__device__ __forceinline__ void cell_update<EulerS, float>(const float* prev, const float* cur, int li, int W, int P,
-                                                           int lvl, const PhaseArgs& a, float out[4])
-{
-    euler_update<float>(prev, cur, li, W, P, lvl, a, out);
-}
-
-// One heat level on the footprint [C-hx, C+hx) x [C-hy, C+hy) of the window:
-// each thread takes a vertical strip of R cells of one column (R chosen so
-// the footprint spreads over the whole workgroup) and walks it top to
-// bottom, keeping the vertical neighbours in registers: about three LDS
-// reads per cell-update.  Cells outside F(l+2) (half-widths hx2, hy2) are
-// also written to the level's global buffer.
-template <typename T>
-__device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ gout,
-                                           int W, int C, const LevelEntry& e, int hx2, int hy2, int ox, int oy,
-                                           int N, T r)
-{
-    const int fw = e.fw, nthr = blockDim.x;
-    for (int t = threadIdx.x; t < fw * e.spc; t += nthr) {
-        const int sidx = qdiv(t, e.inv_fw);
-        const int x = e.x0 + (t - sidx * fw);
-        const int ys = e.y0 + sidx * e.R;
-        const int ye = min(ys + e.R, e.y0 + e.fh);
-        const bool xkeep = (x - C >= -hx2) && (x - C < hx2);
-        const int gx = wrapi(ox + x, N);
-        int gy = wrapi(oy + ys, N);
-        int li = ys * W + x;
-        T up = prev[li - W];
-        T c = prev[li];
-        for (int y = ys; y < ye; ++y) {
-            const T dn = prev[li + W];
-            const T v = heat_update<T>(c, prev[li + 1], prev[li - 1], dn, up, r);
-            cur[li] = v;
-            const bool keep = xkeep && (y - C >= -hy2) && (y - C < hy2);
-            if (!keep) gout[(size_t)gy * N + gx] = v;
-            up = c;
-            c = dn;
-            li += W;
-            gy = (gy + 1 == N) ? 0 : gy + 1;
-        }
-    }
-}
 
 template <class S, typename T>
 __global__ void __launch_bounds__(S::MAXWG) swept_phase_kernel(PhaseArgs a)
@@ -248,11 +60,13 @@ __global__ void __launch_bounds__(S::MAXWG) swept_phase_kernel(PhaseArgs a)
     const int cx = jx * b + ((wx & 1) ? 0 : b / 2);
     const int cy = jy * b + ((wy & 1) ? 0 : b / 2);
     const int ox = cx - C, oy = cy - C;
-    T* g0 = reinterpret_cast<T*>(a.buf0);
-    T* g1 = reinterpret_cast<T*>(a.buf1);
+    T* g0 = reinterpret_cast<T*>(a.out0);
+    T* g1 = reinterpret_cast<T*>(a.out1);
     const int BUF = NVAR * P;  // LDS values per level-parity buffer (address arithmetic keeps ds_* access)
 
-    preload_rings<S, T>(lds, BUF, g0, g1, W, P, N, NN, ox, oy, wx, wy, lo, hi, h, C);
+    const RingSrc<T> src{reinterpret_cast<const T*>(a.buf0), reinterpret_cast<const T*>(a.buf1),
+                         reinterpret_cast<const T*>(a.lvl0), nullptr, nullptr, false};
+    preload_rings<S, T>(lds, BUF, src, W, P, N, NN, ox, oy, wx, wy, lo, hi, h, C);
     __syncthreads();
 
     // level table of this shape type, indexed by the level within its window
@@ -275,23 +89,13 @@ __global__ void __launch_bounds__(S::MAXWG) swept_phase_kernel(PhaseArgs a)
         if constexpr (NVAR == 1) {
             heat_level<T>(prev, cur, gout, W, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
         } else {
-            const int fw = e.fw, cnt = fw * e.fh;
-            for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-                const int q = qdiv(i, e.inv_fw);
-                const int ly = e.y0 + q, lx = e.x0 + (i - q * fw);
-                const int li = ly * W + lx;
-                T out[NVAR];
-                cell_update<S, T>(prev, cur, li, W, P, lvl, a, out);
-#pragma unroll
-                for (int v = 0; v < NVAR; ++v) cur[v * P + li] = out[v];
-                const int dx = lx - C, dy = ly - C;  // in F(l+2) <=> -hw2 <= d < hw2
-                const bool keep = (dx >= -hx2) && (dx < hx2) && (dy >= -hy2) && (dy < hy2);
-                if (!keep) {
-                    const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
-#pragma unroll
-                    for (int v = 0; v < NVAR; ++v) gout[v * NN + gi] = out[v];
-                }
-            }
+            T* pbuf = lds + 2 * BUF;
+            T* fbuf = pbuf + P;
+            const int FS = (b + 1) * b;
+            const bool second = (lvl & 1) == 0;
+            const SweptStore<T, NVAR> st{gout, NN, N, ox, oy, C, hx2, hy2};
+            euler_level<T>(prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second, (T)a.p[0],
+                           (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]), st);
         }
         __syncthreads();
     }
@@ -327,48 +131,49 @@ __global__ void __launch_bounds__(256) heat_standard_kernel(const T* __restrict_
 }
 
 // Euler: one full RK2 step per launch.  A TSxTS output tile loads Q^n on the
-// tile plus a 4-cell halo into LDS, computes Q* on the tile plus 2 cells,
-// then Q^{n+1} on the tile (both stages with the same cell function as the
-// swept kernels).
+// tile plus a 4-cell halo into LDS and runs the same level function as the
+// swept kernels twice: Q* on the tile plus 2 cells, then Q^{n+1} on the tile.
+template <typename T>
+struct TileStore {
+    T* out;
+    size_t NN;
+    int N, gx0, gy0;  // global position of window cell (0, 0)
+    __device__ __forceinline__ void operator()(int lx, int ly, const T* v) const
+    {
+        const size_t gi = (size_t)(gy0 + ly) * N + (gx0 + lx);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) out[c * NN + gi] = v[c];
+    }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                              StdArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
     const int TS = a.ts, N = a.N;
-    const int Wq = TS + 8, Pq = Wq * Wq, Ws = TS + 4, Ps = Ws * Ws;
-    T* q = reinterpret_cast<T*>(smem_raw);
-    T* qs = q + 4 * Pq;
+    const int W = TS + 8, P = W * W, BUF = 4 * P, FS = (TS + 5) * (TS + 4);
     const size_t NN = (size_t)N * N;
     const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS;
-    const float inv_wq = 1.0f / (float)Wq, inv_ws = 1.0f / (float)Ws, inv_ts = 1.0f / (float)TS;
-    for (int i = threadIdx.x; i < Pq; i += blockDim.x) {
-        const int ly = qdiv(i, inv_wq), lx = i - ly * Wq;
+    const float inv_w = 1.0f / (float)W;
+    for (int i = threadIdx.x; i < P; i += blockDim.x) {
+        const int ly = qdiv(i, inv_w), lx = i - ly * W;
         const size_t gi = (size_t)wrapi(ty0 - 4 + ly, N) * N + wrapi(tx0 - 4 + lx, N);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) q[v * Pq + i] = in[v * NN + gi];
+        for (int v = 0; v < 4; ++v) lds[v * P + i] = in[v * NN + gi];
     }
     __syncthreads();
+    T* q0 = lds;
+    T* q1 = lds + BUF;
+    T* pbuf = lds + 2 * BUF;
+    T* fbuf = pbuf + P;
     const T gamma = (T)a.p[0];
-    for (int i = threadIdx.x; i < Ps; i += blockDim.x) {
-        const int ly = qdiv(i, inv_ws), lx = i - ly * Ws;
-        const int qi = (ly + 2) * Wq + (lx + 2);
-        T o[4];
-        euler_cell<T>(q, Pq, Wq, qi, q, Pq, qi, gamma, (T)a.p[1], (T)a.p[2], o);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) qs[v * Ps + i] = o[v];
-    }
+    euler_level<T>(q0, q1, pbuf, fbuf, FS, W, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1], (T)a.p[2],
+                   NoStore{});
     __syncthreads();
-    for (int i = threadIdx.x; i < TS * TS; i += blockDim.x) {
-        const int ly = qdiv(i, inv_ts), lx = i - ly * TS;
-        const int si = (ly + 2) * Ws + (lx + 2);
-        const int qi = (ly + 4) * Wq + (lx + 4);
-        T o[4];
-        euler_cell<T>(qs, Ps, Ws, si, q, Pq, qi, gamma, (T)a.p[3], (T)a.p[4], o);
-        const size_t gi = (size_t)(ty0 + ly) * N + (tx0 + lx);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) out[v * NN + gi] = o[v];
-    }
+    const TileStore<T> st{out, NN, N, tx0 - 4, ty0 - 4};
+    euler_level<T>(q1, q0, pbuf, fbuf, FS, W, P, 4, 4, TS, TS, true, gamma, (T)a.p[3], (T)a.p[4], st);
 }
 
 // --------------------------------------------------------------- reductions
@@ -485,7 +290,13 @@ hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, dou
 size_t euler_standard_lds(int dtype, int ts)
 {
     const size_t s = dtype == 0 ? 8 : 4;
-    return 4 * s * ((size_t)(ts + 8) * (ts + 8) + (size_t)(ts + 4) * (ts + 4));
+    return s * euler_lds_values(ts + 8, (ts + 5) * (ts + 4));
+}
+
+size_t euler_phase_lds(int dtype, int tile)
+{
+    const size_t s = dtype == 0 ? 8 : 4;
+    return s * euler_lds_values(tile + 4, (tile + 1) * tile);
 }
 
 hipError_t set_euler_standard_lds_limit(int dtype, size_t lds)
@@ -518,6 +329,12 @@ hipError_t launch_plane_sums(int dtype, const void* x, int nvar, size_t NN, doub
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(combine_partials, dim3(nvar), dim3(256), 0, st, partials, nparts, 0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const double* partials, int nparts, double* out, hipStream_t st)
+{
+    hipLaunchKernelGGL(combine_partials, dim3(1), dim3(256), 0, st, partials, nparts, 0, out);
     return hipGetLastError();
 }
 

@@ -10,13 +10,14 @@ namespace swept {
 // Per-level launch geometry of one shape type, precomputed on the host
 // (uniform across a workgroup, read with scalar loads).  Footprint
 // [x0, x0+fw) x [y0, y0+fh) in window coordinates; hx2/hy2 = half-widths of
-// the footprint two levels up (0 past the shape's end); R = cells per thread
-// strip and spc = strips per column for the heat strip mapping; inv_fw =
-// 1.0f/fw for the exact float quotient.
+// the footprint two levels up (0 past the shape's end); inv_fw = 1.0f/fw for
+// the exact float quotient of the flattened cell loop.  Heat maps threads
+// onto column pairs: pw = fw/2 pairs per row, each thread walks a vertical
+// strip of R rows of one pair, spc = strips per pair column, inv_pw = 1/pw.
 struct LevelEntry {
-    int x0, y0, fw, fh, R, spc, hx2, hy2;
-    float inv_fw;
-    int pad[3];
+    int x0, y0, fw, fh, hx2, hy2, pw, R, spc;
+    float inv_fw, inv_pw;
+    int pad[5];
 };
 
 // Level table layout (entries indexed by t, the level within the shape's
@@ -27,8 +28,17 @@ inline int level_table_entries(int h) { return 4 * h; }
 // Arguments of one swept phase launch.  p[] holds the scheme constants in
 // double: heat {r}; Euler {gamma, dt/(2dx), dt/(2dy), dt/dx, dt/dy}.
 struct PhaseArgs {
-    void* buf0;   // level-parity buffer 0 (the caller's state)
-    void* buf1;   // level-parity buffer 1 (workspace)
+    void* buf0;   // level-parity buffer 0 (the caller's state): read and written
+    void* buf1;   // level-parity buffer 1 (workspace): read and written
+    void* out0;   // where stores go (normally buf0/buf1; the adjoint's Bridges recompute writes elsewhere)
+    void* out1;
+    const void* lvl0;  // level-0 state (normally buf0)
+    const void* q0;    // adjoint only: the Bridges' strips, read by the Octahedron recompute
+    const void* q1;
+    void* lam0;        // adjoint only: lambda level-parity buffers (reversed time)
+    void* lam1;
+    double* partials;  // adjoint only: one pairing partial sum per workgroup
+    int shift;         // adjoint only: 1 = the reversed sweep runs on the other tiling
     int N;        // cells per side
     int tile;     // b
     int h;        // b / (2n)
@@ -49,8 +59,15 @@ hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t 
 hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds);
 hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, double r, hipStream_t st);
 size_t euler_standard_lds(int dtype, int ts);
+size_t euler_phase_lds(int dtype, int tile);  // LDS bytes of an Euler swept workgroup
 hipError_t set_euler_standard_lds_limit(int dtype, size_t lds);
 hipError_t launch_euler_standard(int dtype, const void* in, void* out, const StdArgs& a, hipStream_t st);
+size_t adjoint_lds(int dtype, int tile, int pk_max, int wg);
+hipError_t set_adjoint_lds_limit(int dtype, size_t lds);
+hipError_t launch_adjoint_phase(int dtype, const PhaseArgs& a, int pk_max, int wg, size_t lds, hipStream_t st);
+hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const void* Tm, int N, double r,
+                               double* partials, int nblocks, hipStream_t st);
+hipError_t launch_combine(const double* partials, int nparts, double* out, hipStream_t st);
 hipError_t launch_plane_sums(int dtype, const void* x, int nvar, size_t NN, double* partials, int nparts,
                              double* out, hipStream_t st);
 hipError_t launch_cfl_max(int dtype, const void* q, size_t NN, double gamma, double dx, double dy, double* partials,

@@ -95,37 +95,4 @@ __device__ __forceinline__ void face_flux(const T qa[4], const T qb[4], const T 
     for (int k = 0; k < 4; ++k) out[k] = T(0.5) * ((fR[k] + fL[k]) + s * (L[k] - R[k]));
 }
 
-// One RK stage at one cell (App. B, explicit midpoint):
-//   out = (base - cx (F_{i+1/2} - F_{i-1/2})) - cy (G_{j+1/2} - G_{j-1/2}),
-// fluxes evaluated on the field at `f` (plane stride fp, row stride fw,
-// cell offset fi) and the base value read from `b` (plane stride bp, cell
-// offset bi).  First stage: base = flux field, (cx, cy) = dt/(2dx), dt/(2dy);
-// second stage: base = Q^n, flux field = Q*, (cx, cy) = dt/dx, dt/dy.
-template <typename T>
-__device__ __forceinline__ void euler_cell(const T* __restrict__ f, int fp, int fw, int fi, const T* b, int bp,
-                                           int bi, T gamma, T cx, T cy, T out[4])
-{
-    T q[9][4];  // centre, x-2, x-1, x+1, x+2, y-2, y-1, y+1, y+2
-    const int off[9] = {0, -2, -1, 1, 2, -2 * fw, -fw, fw, 2 * fw};
-#pragma unroll
-    for (int s = 0; s < 9; ++s)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) q[s][k] = f[k * fp + fi + off[s]];
-    const T gm1 = gamma - T(1);
-    T p[9];
-#pragma unroll
-    for (int s = 0; s < 9; ++s) p[s] = pressure(q[s], gm1);
-    T fm[4], fpl[4], gm[4], gp[4];
-    face_flux<T, 1>(q[1], q[2], q[0], q[3], p[1], p[2], p[0], p[3], gamma, fm);   // x face i-1/2
-    face_flux<T, 1>(q[2], q[0], q[3], q[4], p[2], p[0], p[3], p[4], gamma, fpl);  // x face i+1/2
-    face_flux<T, 2>(q[5], q[6], q[0], q[7], p[5], p[6], p[0], p[7], gamma, gm);   // y face j-1/2
-    face_flux<T, 2>(q[6], q[0], q[7], q[8], p[6], p[0], p[7], p[8], gamma, gp);   // y face j+1/2
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const T dF = fpl[k] - fm[k];
-        const T dG = gp[k] - gm[k];
-        out[k] = (b[k * bp + bi] - cx * dF) - cy * dG;
-    }
-}
-
 }  // namespace swept

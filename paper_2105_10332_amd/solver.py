@@ -85,6 +85,31 @@ class SweptSolver:
         check(lib().swept_conserved(self._ctx, out))
         return list(out)
 
+    # ---- adjoint (heat) ----
+    def swept_tape_bytes(self, n_steps: int) -> int:
+        out = ctypes.c_size_t(0)
+        check(lib().swept_tape_bytes(self._ctx, int(n_steps), ctypes.byref(out)))
+        return out.value
+
+    def new_tape(self, n_steps: int) -> torch.Tensor:
+        return torch.empty(self.swept_tape_bytes(n_steps), dtype=torch.uint8, device=self.state.device)
+
+    def swept_advance_checkpointed(self, n_steps: int, tape: torch.Tensor):
+        check(lib().swept_set_stream(self._ctx, _stream_ptr()))
+        check(lib().swept_advance_checkpointed(self._ctx, int(n_steps), _dev_ptr(tape), tape.numel()))
+        return self.state
+
+    def swept_adjoint(self, n_steps: int, tape: torch.Tensor, gTM: torch.Tensor, gT0: torch.Tensor) -> float:
+        """Writes dJ/dT^0 into gT0 for dJ/dT^M = gTM; returns dJ/dalpha."""
+        for t in (gTM, gT0):
+            if t.dtype != self.state.dtype or t.shape != self.state.shape:
+                raise ValueError("gradients must match the state's shape and dtype")
+        out = ctypes.c_double(0.0)
+        check(lib().swept_set_stream(self._ctx, _stream_ptr()))
+        check(lib().swept_adjoint(self._ctx, int(n_steps), _dev_ptr(tape), tape.numel(), _dev_ptr(gTM),
+                                  _dev_ptr(gT0), ctypes.byref(out)))
+        return out.value
+
     def close(self):
         if self._ctx:
             lib().swept_destroy(self._ctx)
@@ -95,6 +120,39 @@ class SweptSolver:
             self.close()
         except Exception:
             pass
+
+
+class SweptHeatAdvance(torch.autograd.Function):
+    """T^M = swept heat advance of T^0 by n_steps with diffusivity alpha, differentiable
+    in T^0 and alpha through the hand-written swept adjoint (swept_adjoint).
+
+    apply(T0, alpha, n_steps, dt, length=1.0, tile=0): T0 an (N, N) GPU tensor,
+    alpha a 0-d tensor (or float).  The forward records a checkpoint per swept
+    cycle; backward runs the reverse sweep and returns (dJ/dT0, dJ/dalpha)."""
+
+    @staticmethod
+    def forward(ctx, T0, alpha, n_steps, dt, length=1.0, tile=0):
+        state = T0.detach().clone().contiguous()
+        a = float(alpha)
+        solver = SweptSolver(HEAT, state, dt=dt, length=length, alpha=a, tile=tile)
+        tape = solver.new_tape(n_steps)
+        solver.swept_advance_checkpointed(n_steps, tape)
+        ctx.solver, ctx.tape, ctx.n = solver, tape, int(n_steps)
+        ctx.alpha_is_tensor = torch.is_tensor(alpha)
+        if ctx.alpha_is_tensor:
+            ctx.alpha_meta = (alpha.shape, alpha.dtype, alpha.device)
+        return state.clone()
+
+    @staticmethod
+    def backward(ctx, gTM):
+        gTM = gTM.contiguous()
+        gT0 = torch.empty_like(gTM)
+        dalpha = ctx.solver.swept_adjoint(ctx.n, ctx.tape, gTM, gT0)
+        ga = None
+        if ctx.alpha_is_tensor:
+            shape, dtype, device = ctx.alpha_meta
+            ga = torch.full(shape, dalpha, dtype=dtype, device=device)
+        return gT0, ga, None, None, None, None
 
 
 def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 1.4) -> float:
@@ -109,4 +167,4 @@ def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 
     return out.value
 
 
-__all__ = ["SweptSolver", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT", "EULER", "_lib"]
+__all__ = ["SweptSolver", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT", "EULER", "_lib"]

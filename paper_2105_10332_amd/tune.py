@@ -13,7 +13,6 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LDS_MAX = 160 * 1024
 
 
 def cache_path() -> str:
@@ -52,18 +51,25 @@ def save_cache(c: dict):
 
 
 def candidates(kind: str, dtype: str, n: int):
-    """Valid tiles (b > 2n, b % 2n == 0, n_grid % b == 0, n_grid >= 2b, LDS fits) x workgroup sizes."""
-    rad = 1 if kind == "heat" else 2
-    nvar = 1 if kind == "heat" else 4
-    S = 8 if dtype == "f64" else 4
+    """Tiles the library accepts for this grid (b > 2n, b % 2n == 0, n_grid % b == 0,
+    n_grid >= 2b, LDS fits; checked by swept_workspace_bytes on the host) x workgroup sizes."""
+    from . import _lib
+    from .solver import EULER, HEAT, make_problem, swept_workspace_bytes
+
+    import torch
+
+    k = HEAT if kind == "heat" else EULER
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    dt = 0.2 / (n * n) if kind == "heat" else 1e-4  # any valid time step: only the geometry matters here
+    prob = make_problem(k, n, tdt, dt, 1.0 if kind == "heat" else 10.0, 1.0)
     tiles = []
     for b in (8, 12, 16, 24, 32, 48, 64):
-        if b <= 2 * rad or b % (2 * rad) or n % b or n < 2 * b:
-            continue
-        if 2 * nvar * (b + 2 * rad) ** 2 * S > LDS_MAX:
+        try:
+            swept_workspace_bytes(prob, b, 0)
+        except _lib.SweptError:
             continue
         tiles.append(b)
-    wgs = (256, 512, 1024) if kind == "heat" else (128, 256)
+    wgs = (64, 128, 256, 512, 1024) if kind == "heat" else (128, 256)
     return [(b, wg) for b in tiles for wg in wgs]
 
 

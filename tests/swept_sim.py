@@ -52,6 +52,7 @@ class Geom:
     b: int      # tile edge
     n: int      # stencil radius per level
     L: int      # final level
+    shift: int = 0  # 1: even diamonds centred at tile edges, odd ones at tile centres (the other tiling)
 
     @property
     def h(self) -> int:
@@ -65,7 +66,7 @@ class Geom:
         return 2 * math.ceil(self.L / self.h) + 1 if self.L > 0 else 0
 
     def centre(self, w: int, j: int) -> int:
-        return j * self.b + (self.b // 2 if w % 2 == 0 else 0)
+        return j * self.b + (self.b // 2 if (w + self.shift) % 2 == 0 else 0)
 
     def half_width(self, w: int, lvl: int) -> int:
         t = lvl - (w - 1) * self.h

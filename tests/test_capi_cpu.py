@@ -73,9 +73,12 @@ def test_validation_codes(prob, tile, wg, code):
     assert _lib.last_error()
 
 
-def test_fp32_euler_tile64_fits_lds():
-    rc, _ = _ws(euler(256, dtype=1), 64)
-    assert rc == 0
+def test_euler_lds_limits():
+    """Euler keeps two state windows, a pressure plane and a face buffer in LDS:
+    FP64 fits up to b = 32, FP32 b = 64 does not."""
+    assert _ws(euler(256, dtype=0), 32)[0] == 0
+    assert _ws(euler(256, dtype=1), 32)[0] == 0
+    assert _ws(euler(256, dtype=1), 64)[0] == CODES["SWEPT_ESHAPE"]
 
 
 def test_init_rejects_bad_pointers_and_small_workspace():
