@@ -1,25 +1,29 @@
-"""Benchmark: swept-rule heat diffusion on one MI355X.
+"""Benchmark of the swept-rule solver on one MI355X.
 
-Workload (one "step" of this benchmark = one whole swept advance):
-heat equation on the periodic unit square, 4096 x 4096 cells, forward-Euler
+Default workload (one bench "step" = one whole swept advance): heat
+diffusion on the periodic unit square, 4096 x 4096 cells, forward-Euler
 5-point stencil, r = alpha dt / dx^2 = 0.2, 1000 time steps per advance,
-initial state = 16 seeded random Fourier modes (wavenumbers 1-32, amplitudes
-N(0,1)/k).  The state is resident in HBM before timing starts; each timed
-step advances it 1000 more time steps in place.
+initial state = 16 seeded random Fourier modes.  The state is resident in
+HBM before timing starts; each timed step advances it 1000 more time steps
+in place.
 
-Reported: cell-updates/s of the swept solver (value), the Standard solver's
-rate on the same input and its speedup S = R_standard / R_swept (Eq. 3), the
-effective bandwidth (bytes the Standard solver moves per step / time), the
-roofline of the dominant kernel (the swept phase kernel) and the CPU oracle
-timed on a bounded sample of the same workload.
+Reported: cell-updates/s of the swept solver (value), the Standard
+solver's rate on the same input and the paper's speedup S = R_standard /
+R_swept (Eq. 3), the effective bandwidth (bytes the Standard solver would
+move / time), the roofline of the dominant kernel (the swept phase kernel)
+and the CPU oracle timed on a bounded sample of the same workload.
 
-Usage: python bench.py [--steps K] [--warmup W] [--dtype f64|f32] [--tile B]
+Other workloads (--workload): euler (2048^2 vortex, 500 RK2 steps per
+step), adjoint (1024^2 FP32 heat, 2000 steps: forward with checkpoints +
+reverse sweep per step), batch (48 heat + 16 Euler problems, FP32, 200 steps,
+one persistent launch per step).
+
+Usage: python bench.py [--steps K] [--warmup W] [--dtype f64|f32] [--tile B] [--workload W]
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -27,10 +31,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-N = 4096
-STEPS_PER_ADVANCE = 1000
-R = 0.2
 HBM_PEAK_GBS = 8000.0
+METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB/s"
 
 
 def parse():
@@ -38,18 +40,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--workload", choices=["heat", "euler", "adjoint", "batch"], default="heat")
+    ap.add_argument("--dtype", choices=["f64", "f32"], default=None)
     ap.add_argument("--tile", type=int, default=0, help="0: tuned or default tile")
-    ap.add_argument("--n", type=int, default=N)
-    ap.add_argument("--advance-steps", type=int, default=STEPS_PER_ADVANCE)
+    ap.add_argument("--wg", type=int, default=0, help="0: tuned or library default")
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--advance-steps", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-standard", action="store_true")
     return ap.parse_args()
 
 
-def time_events(fn, k, stream):
+def timed(fn, k):
+    """Run fn k times between two events on the current stream; (seconds, wall seconds)."""
     import torch
 
+    stream = torch.cuda.current_stream()
     start = torch.cuda.Event(enable_timing=True)
     end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -59,13 +65,16 @@ def time_events(fn, k, stream):
         fn()
     end.record(stream)
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    return start.elapsed_time(end) / 1e3, wall
+    return start.elapsed_time(end) / 1e3, time.perf_counter() - t0
 
 
-def cpu_baseline(dtype_np, n, budget_s=12.0):
-    """The oracle, as it is, on the host cores: one step to size the sample, then a
-    bounded number of steps of the same 4096^2 workload."""
+def cores():
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+
+
+def cpu_heat(dtype_np, n, r, budget_s=12.0):
+    """The oracle as it is on the host cores: one step to size the sample, then a bounded
+    number of Standard steps of the same grid."""
     import numpy as np
 
     import oracle
@@ -73,93 +82,240 @@ def cpu_baseline(dtype_np, n, budget_s=12.0):
 
     T0 = problems.heat_fourier_modes(n).astype(dtype_np)
     t = time.perf_counter()
-    T1 = oracle.heat_run(T0, R, 1)
+    T1 = oracle.heat_run(T0, r, 1)
     one = time.perf_counter() - t
     k = max(1, min(1000, int(budget_s / max(one, 1e-6))))
     t = time.perf_counter()
-    oracle.heat_run(T1, R, k)
+    oracle.heat_run(T1, r, k)
     el = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    return {"value": n * n * k / el, "unit": "cell-updates/s", "cores": cores, "kind": "oracle",
+    return {"value": n * n * k / el, "unit": "cell-updates/s", "cores": cores(), "kind": "oracle",
             "sample": f"heat {n}x{n} {np.dtype(dtype_np).name}, {k} Standard steps of the C oracle "
                       f"(OpenMP over rows), {el:.1f} s"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (the swept path here is single-device); got --gpus {args.gpus}",
-              file=sys.stderr)
-        sys.exit(2)
+def cpu_euler(dtype_np, n, dt, budget_s=12.0):
+    import numpy as np
+
+    import oracle
+    from paper_2105_10332_amd import problems
+
+    Q0 = problems.shu_vortex(n).astype(dtype_np)
+    t = time.perf_counter()
+    Q1 = oracle.euler_run(Q0, dt, 10 / n, 10 / n, 1.4, 1)
+    one = time.perf_counter() - t
+    k = max(1, min(500, int(budget_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, k)
+    el = time.perf_counter() - t
+    return {"value": n * n * k / el, "unit": "cell-steps/s", "cores": cores(), "kind": "oracle",
+            "sample": f"Euler vortex {n}x{n} {np.dtype(dtype_np).name}, {k} RK2 steps of the C oracle, {el:.1f} s"}
+
+
+def base_record(args, value, unit, sec, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": sec / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def roofline(plan, S, nvar, launches, sec, kernel):
+    """Algorithmic HBM bytes of the swept phase kernel per launch / its average launch time."""
+    alg = (plan["loads"] + plan["stores"]) * S * nvar / plan["launches"]
+    avg = sec / launches
+    ach = alg / avg / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+            "traffic": None, "kernel": kernel, "alg_bytes_per_launch": alg, "avg_launch_us": avg * 1e6}
+
+
+def run_heat(args):
     import numpy as np
     import torch
 
     from paper_2105_10332_amd import geometry, problems, tune
     from paper_2105_10332_amd.solver import HEAT, SweptSolver
 
-    dev = torch.device("cuda", 0)
-    tdt = torch.float64 if args.dtype == "f64" else torch.float32
-    S = 8 if args.dtype == "f64" else 4
-    n, M = args.n, args.advance_steps
-    tile = args.tile or tune.best_tile("heat", args.dtype, n)
+    dt_name = args.dtype or "f64"
+    tdt = torch.float64 if dt_name == "f64" else torch.float32
+    S = 8 if dt_name == "f64" else 4
+    n, M, r = args.n or 4096, args.advance_steps or 1000, 0.2
+    tile, wg = tune.best("heat", dt_name, n)
+    tile, wg = args.tile or tile, args.wg or wg
     T0 = problems.heat_fourier_modes(n)
     dx = 1.0 / n
-    state = torch.tensor(T0, dtype=tdt, device=dev)
-    solver = SweptSolver(HEAT, state, dt=R * dx * dx, length=1.0, alpha=1.0, tile=tile)
-    stream = torch.cuda.current_stream()
-
+    state = torch.tensor(T0, dtype=tdt, device="cuda")
+    solver = SweptSolver(HEAT, state, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, wg=wg)
     for _ in range(args.warmup):
         solver.swept_advance(M)
-    sec, wall = time_events(lambda: solver.swept_advance(M), args.steps, stream)
+    sec, wall = timed(lambda: solver.swept_advance(M), args.steps)
     updates = n * n * M * args.steps
     rate = updates / sec
-
     plan = geometry.totals(n, tile, 1, M)
-    launches = plan["launches"] * args.steps
-    avg_launch_s = sec / launches
-    alg_bytes_per_launch = (plan["loads"] + plan["stores"]) * S / plan["launches"]
-    achieved = alg_bytes_per_launch / avg_launch_s / 1e9
-
-    std = None
+    cfg = {"workload": f"heat {n}x{n} periodic, 5-point forward Euler, r=0.2, {M} time steps per bench step, "
+                       f"16 seeded Fourier modes; swept tile {tile}",
+           "tile": tile, "wg": solver.info.wg, "time_steps_per_step": M, "launches_per_step": plan["launches"]}
+    out = base_record(args, rate, "cell-updates/s", sec, dt_name, cfg)
+    out["effective_GBps"] = 2 * S * updates / sec / 1e9
+    out["roofline"] = roofline(plan, S, 1, plan["launches"] * args.steps, sec, "swept_phase_kernel<HeatS>")
     if not args.no_standard:
-        st_state = torch.tensor(T0, dtype=tdt, device=dev)
-        st_solver = SweptSolver(HEAT, st_state, dt=R * dx * dx, length=1.0, alpha=1.0, tile=tile)
-        st_solver.standard_advance(M)
-        k_std = max(1, min(args.steps, 3))
-        ssec, _ = time_events(lambda: st_solver.standard_advance(M), k_std, stream)
-        srate = n * n * M * k_std / ssec
-        std = {"value": srate, "unit": "cell-updates/s", "ms_per_advance": ssec / k_std * 1e3,
-               "achieved_GBps": 2 * S * n * n * M * k_std / ssec / 1e9}
-
-    out = {
-        "metric": "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB/s",
-        "value": rate,
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": sec / args.steps * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": args.dtype,
-        "data": "synthetic",
-        "config": {"workload": f"heat {n}x{n} periodic, 5-point forward Euler, r=0.2, {M} time steps per "
-                               f"bench step, 16 seeded Fourier modes; swept tile {tile}",
-                   "tile": tile, "time_steps_per_step": M, "launches_per_step": plan["launches"]},
-        "effective_GBps": 2 * S * updates / sec / 1e9,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "swept_phase_kernel<HeatS>",
-                     "alg_bytes_per_launch": alg_bytes_per_launch, "avg_launch_us": avg_launch_s * 1e6},
-        "standard": std,
-        "speedup_vs_standard": (rate / std["value"]) if std else None,
-        "wall_s": wall,
-    }
+        st = torch.tensor(T0, dtype=tdt, device="cuda")
+        ss = SweptSolver(HEAT, st, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile)
+        ss.standard_advance(M)
+        k = max(1, min(args.steps, 3))
+        ssec, _ = timed(lambda: ss.standard_advance(M), k)
+        out["standard"] = {"value": n * n * M * k / ssec, "unit": "cell-updates/s", "ms_per_advance": ssec / k * 1e3,
+                           "achieved_GBps": 2 * S * n * n * M * k / ssec / 1e9}
+        out["speedup_vs_standard"] = rate / out["standard"]["value"]
+    out["wall_s"] = wall
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(np.float64 if args.dtype == "f64" else np.float32, n)
-    solver.close()
-    print(json.dumps(out), flush=True)
+        out["cpu_baseline"] = cpu_heat(np.float64 if dt_name == "f64" else np.float32, n, r)
+    return out
+
+
+def run_euler(args):
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2105_10332_amd import geometry, problems, tune
+    from paper_2105_10332_amd.solver import EULER, SweptSolver, swept_cfl_dt
+
+    dt_name = args.dtype or "f64"
+    tdt = torch.float64 if dt_name == "f64" else torch.float32
+    S = 8 if dt_name == "f64" else 4
+    n, M = args.n or 2048, args.advance_steps or 500
+    tile, wg = tune.best("euler", dt_name, n)
+    tile, wg = args.tile or tile, args.wg or wg
+    Q0 = problems.shu_vortex(n)
+    q = torch.tensor(Q0, dtype=tdt, device="cuda")
+    dt = swept_cfl_dt(torch.tensor(Q0, device="cuda"), 10.0, 0.4)
+    solver = SweptSolver(EULER, q, dt=dt, length=10.0, gamma=1.4, tile=tile, wg=wg)
+    for _ in range(args.warmup):
+        solver.swept_advance(M)
+    sec, wall = timed(lambda: solver.swept_advance(M), args.steps)
+    cells = n * n * M * args.steps
+    rate = cells / sec
+    plan = geometry.totals(n, tile, 2, 2 * M, True)
+    cfg = {"workload": f"Euler {n}x{n} periodic [0,10]^2, gamma 1.4, vortex eps 5 on (1,1), minmod + Rusanov, "
+                       f"RK2, CFL 0.4 (dt {dt:.6e}), {M} steps per bench step; swept tile {tile}",
+           "tile": tile, "time_steps_per_step": M, "launches_per_step": plan["launches"]}
+    out = base_record(args, rate, "cell-steps/s", sec, dt_name, cfg)
+    out["effective_GBps"] = 8 * S * cells / sec / 1e9
+    out["roofline"] = roofline(plan, S, 4, plan["launches"] * args.steps, sec, "swept_phase_kernel<EulerS>")
+    if not args.no_standard:
+        st = torch.tensor(Q0, dtype=tdt, device="cuda")
+        ss = SweptSolver(EULER, st, dt=dt, length=10.0, gamma=1.4, tile=tile)
+        ss.standard_advance(M)
+        ssec, _ = timed(lambda: ss.standard_advance(M), 1)
+        out["standard"] = {"value": n * n * M / ssec, "unit": "cell-steps/s", "ms_per_advance": ssec * 1e3}
+        out["speedup_vs_standard"] = rate / out["standard"]["value"]
+    out["wall_s"] = wall
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_euler(np.float64 if dt_name == "f64" else np.float32, n, dt)
+    return out
+
+
+def run_adjoint(args):
+    import numpy as np
+    import torch
+
+    from paper_2105_10332_amd import problems
+    from paper_2105_10332_amd.solver import HEAT, SweptSolver
+
+    dt_name = args.dtype or "f32"
+    tdt = torch.float64 if dt_name == "f64" else torch.float32
+    n, M = args.n or 1024, args.advance_steps or 2000
+    tile = args.tile or 32
+    dx = 1.0 / n
+    T0 = torch.tensor(problems.heat_fourier_modes(n, seed=problems.SEED_ADJ_T0), dtype=tdt, device="cuda")
+    Ts = torch.tensor(problems.heat_fourier_modes(n, seed=problems.SEED_ADJ_TARGET), dtype=tdt, device="cuda")
+    x = T0.clone()
+    s = SweptSolver(HEAT, x, dt=0.2 * dx * dx, length=1.0, alpha=1.0, tile=tile, wg=args.wg)
+    tape = s.new_tape(M)
+    gT0 = torch.empty_like(x)
+
+    def one():
+        x.copy_(T0)
+        s.swept_advance_checkpointed(M, tape)
+        s.swept_adjoint(M, tape, x - Ts, gT0)
+
+    for _ in range(args.warmup):
+        one()
+    sec, wall = timed(one, args.steps)
+    fsec, _ = timed(lambda: s.swept_advance(M), 1)
+    csec, _ = timed(lambda: s.swept_advance_checkpointed(M, tape), 1)
+    gTM = x - Ts
+    asec, _ = timed(lambda: s.swept_adjoint(M, tape, gTM, gT0), 1)
+    cfg = {"workload": f"adjoint of heat {n}x{n} periodic, r=0.2, {M} steps, loss 1/2 sum (T^M - T*)^2, "
+                       f"gradients wrt T0 and alpha, checkpoint per swept cycle of {tile // 2} steps; tile {tile}",
+           "tile": tile}
+    out = base_record(args, n * n * M * args.steps / sec, "cell-updates/s (forward+adjoint)", sec, dt_name, cfg)
+    out["forward_ms"] = fsec * 1e3
+    out["forward_checkpointed_ms"] = csec * 1e3
+    out["adjoint_ms"] = asec * 1e3
+    out["adjoint_over_forward"] = asec / fsec
+    out["wall_s"] = wall
+    return out
+
+
+def run_batch(args):
+    import torch
+
+    import oracle
+    from paper_2105_10332_amd import problems, tune
+    from paper_2105_10332_amd.solver import EULER, HEAT, SweptBatch, SweptSolver
+
+    dt_name = args.dtype or "f32"
+    tdt = torch.float64 if dt_name == "f64" else torch.float32
+    M = args.advance_steps or 200
+    items, cells = [], 0
+    for it in problems.batch_ensemble():
+        n = it.n
+        if it.kind == "heat":
+            x = torch.tensor(problems.heat_fourier_modes(n, seed=it.seed), dtype=tdt, device="cuda")
+            tile = tune.best_tile("heat", dt_name, n)
+            items.append((HEAT, x, it.r / n / n, 1.0, 1.0, 1.4, tile))
+        else:
+            q0 = problems.shu_vortex(n, eps=it.eps)
+            dt = oracle.cfl_dt(q0, 10 / n, 10 / n, 1.4, 0.4)
+            tile = tune.best_tile("euler", dt_name, n)
+            items.append((EULER, torch.tensor(q0, dtype=tdt, device="cuda"), dt, 10.0, 1.0, 1.4, tile))
+        cells += n * n * M
+    init = [it[1].clone() for it in items]
+    b = SweptBatch(items)
+
+    def one():
+        for it, x0 in zip(items, init):
+            it[1].copy_(x0)
+        b.swept_batch_advance(M)
+
+    for _ in range(args.warmup):
+        one()
+    sec, wall = timed(one, args.steps)
+    # the same problems one after another with their own swept advance (reference rate)
+    solvers = [SweptSolver(k, x, dt=dt, length=L, alpha=a, gamma=g, tile=t) for (k, x, dt, L, a, g, t) in items]
+
+    def seq():
+        for sv, x0 in zip(solvers, init):
+            sv.state.copy_(x0)
+            sv.swept_advance(M)
+
+    ssec, _ = timed(seq, 1)
+    cfg = {"workload": f"batch of 48 heat (edges 128-1024, r 0.05-0.24) + 16 Euler vortex (edges 256-1024, "
+                       f"eps 1-5) problems, {M} steps each, one persistent launch; grid {b.grid} workgroups",
+           "problems": len(items), "grid": b.grid}
+    out = base_record(args, cells * args.steps / sec, "cell-updates/s", sec, dt_name, cfg)
+    out["sequential_swept"] = {"value": cells / ssec, "unit": "cell-updates/s", "ms": ssec * 1e3}
+    out["wall_s"] = wall
+    return out
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU (the swept path here is single-device); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+    fn = {"heat": run_heat, "euler": run_euler, "adjoint": run_adjoint, "batch": run_batch}[args.workload]
+    print(json.dumps(fn(args)), flush=True)
 
 
 if __name__ == "__main__":

@@ -179,6 +179,30 @@ int swept_adjoint(swept_ctx* ctx, int64_t n_steps, void* d_tape, size_t tape_byt
 
 int swept_destroy(swept_ctx* ctx);
 
+/* ---- Batched ensemble in one persistent launch (not in the paper) ---------
+ * count problems of uneven size and kind (heat and Euler mixed, one dtype)
+ * advanced together by a single cooperative kernel: the grid holds what the
+ * GPU keeps resident, and every workgroup walks global phases g = 0, 1, ...,
+ * taking the shape instances of phase g of every problem (each problem has
+ * 1 + 2 ceil(L/h) phases for its own tile), with a grid barrier between
+ * global phases.  Every problem's result equals its own swept_advance bit
+ * for bit.  Workgroups have 256 threads; tunes[q].tile (or 0 = default)
+ * picks each problem's tile, tunes may be NULL. */
+typedef struct swept_batch swept_batch;
+
+int swept_batch_workspace_bytes(const swept_problem* probs, const swept_tuning* tunes, int32_t count,
+                                size_t* bytes);
+/* d_states[q]: problem q's state (layout as above), advanced in place. */
+int swept_batch_init(swept_batch** ctx, const swept_problem* probs, const swept_tuning* tunes,
+                     void* const* d_states, int32_t count, void* d_work, size_t work_bytes, void* hip_stream);
+/* n_steps time steps for every problem, one persistent launch.  Asynchronous. */
+int swept_batch_advance(swept_batch* ctx, int64_t n_steps);
+int swept_batch_query(const swept_batch* ctx, int32_t q, swept_info* info);
+/* Workgroups of the persistent launch (resident capacity for its LDS). */
+int swept_batch_grid(const swept_batch* ctx, int32_t* grid);
+int swept_batch_set_stream(swept_batch* ctx, void* hip_stream);
+int swept_batch_destroy(swept_batch* ctx);
+
 /* Message for the last error on this thread ("" if none). */
 const char* swept_last_error(void);
 

@@ -61,6 +61,15 @@ _SIGS = {
     "swept_tape_bytes": [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
     "swept_advance_checkpointed": [_P, ctypes.c_int64, _P, ctypes.c_size_t],
     "swept_adjoint": [_P, ctypes.c_int64, _P, ctypes.c_size_t, _P, _P, ctypes.POINTER(ctypes.c_double)],
+    "swept_batch_workspace_bytes": [ctypes.POINTER(Problem), ctypes.POINTER(Tuning), ctypes.c_int32,
+                                    ctypes.POINTER(ctypes.c_size_t)],
+    "swept_batch_init": [ctypes.POINTER(_P), ctypes.POINTER(Problem), ctypes.POINTER(Tuning), ctypes.POINTER(_P),
+                         ctypes.c_int32, _P, ctypes.c_size_t, _P],
+    "swept_batch_advance": [_P, ctypes.c_int64],
+    "swept_batch_query": [_P, ctypes.c_int32, ctypes.POINTER(Info)],
+    "swept_batch_grid": [_P, ctypes.POINTER(ctypes.c_int32)],
+    "swept_batch_set_stream": [_P, _P],
+    "swept_batch_destroy": [_P],
 }
 
 _lib = None

@@ -1,0 +1,83 @@
+// batch.hip -- many swept problems of uneven size in one persistent launch.
+//
+// The grid is sized to what the GPU holds resident (cooperative launch), and
+// every workgroup walks global phases g = 0, 1, ...: in phase g it takes,
+// grid-stride, the shape instances of phase g of every problem that has one
+// (each problem has 1 + 2 ceil(L/h) phases for its own tile and level count),
+// runs each exactly like the single-problem phase kernel, and then waits at
+// a grid barrier.  Problems are independent, so one barrier per global phase
+// is the only synchronisation; heat and Euler instances share the launch.
+#include <hip/hip_cooperative_groups.h>
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace swept {
+
+namespace cg = cooperative_groups;
+
+__device__ __forceinline__ int problem_phases(const PhaseArgs& a, long long n_steps)
+{
+    const long long L = n_steps * (a.kind == 0 ? 1 : 2);
+    return L > 0 ? 2 * (int)((L + a.h - 1) / a.h) + 1 : 0;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBatchWG) batch_kernel(const PhaseArgs* __restrict__ probs, int count,
+                                                          int nphase_max, long long n_steps)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int pre[kBatchMax + 1];
+    cg::grid_group grid = cg::this_grid();
+    for (int gp = 0; gp < nphase_max; ++gp) {
+        if (threadIdx.x == 0) {  // items of this global phase, problem by problem
+            int tot = 0;
+            for (int q = 0; q < count; ++q) {
+                pre[q] = tot;
+                const PhaseArgs& a = probs[q];
+                const int t2 = a.tiles * a.tiles;
+                if (gp < problem_phases(a, n_steps)) tot += (gp & 1) ? 2 * t2 : t2;
+            }
+            pre[count] = tot;
+        }
+        __syncthreads();
+        const int total = pre[count];
+        for (int it = blockIdx.x; it < total; it += gridDim.x) {
+            int lo = 0, hi = count;  // largest q with pre[q] <= it
+            while (hi - lo > 1) {
+                const int mid = (lo + hi) >> 1;
+                if (pre[mid] <= it) lo = mid;
+                else hi = mid;
+            }
+            PhaseArgs a = probs[lo];
+            a.phase = gp;
+            a.L = (int)(n_steps * (a.kind == 0 ? 1 : 2));
+            if (a.kind == 0) phase_instance<HeatS, T>(a, it - pre[lo], smem_raw);
+            else phase_instance<EulerS, T>(a, it - pre[lo], smem_raw);
+            __syncthreads();
+        }
+        grid.sync();
+    }
+}
+
+hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu)
+{
+    const void* f = dtype == 0 ? (const void*)batch_kernel<double> : (const void*)batch_kernel<float>;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, kBatchWG, lds);
+}
+
+hipError_t set_batch_lds_limit(int dtype, size_t lds)
+{
+    const void* f = dtype == 0 ? (const void*)batch_kernel<double> : (const void*)batch_kernel<float>;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphase_max, long long n_steps, int grid,
+                        size_t lds, hipStream_t st)
+{
+    void* args[] = {(void*)&d_args, (void*)&count, (void*)&nphase_max, (void*)&n_steps};
+    const void* f = dtype == 0 ? (const void*)batch_kernel<double> : (const void*)batch_kernel<float>;
+    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kBatchWG), args, (unsigned int)lds, st);
+}
+
+}  // namespace swept

@@ -7,8 +7,10 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "../../include/swept.h"
 #include "launch.h"
@@ -578,6 +580,206 @@ int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, voi
 int swept_destroy(swept_ctx* c)
 {
     delete c;
+    return SWEPT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- batch
+
+struct swept_batch {
+    int count = 0, dtype = 0;
+    hipStream_t stream = nullptr;
+    std::vector<swept_problem> probs;
+    std::vector<Derived> d;
+    std::vector<void*> states, buf1s;
+    swept::PhaseArgs* dev_args = nullptr;
+    size_t lds = 0;
+    int grid = 0;
+};
+
+namespace {
+
+struct BatchLayout {
+    std::vector<size_t> buf1_off, tab_off;
+    size_t args_off, total;
+};
+
+int batch_derive(const swept_problem* probs, const swept_tuning* tunes, int32_t count, std::vector<Derived>* d,
+                 BatchLayout* lay)
+{
+    if (!probs) return fail(SWEPT_EINVAL, "problems is NULL");
+    if (count < 1 || count > swept::kBatchMax)
+        return fail(SWEPT_EINVAL, "count=%d outside [1, %d]", count, swept::kBatchMax);
+    d->resize(count);
+    lay->buf1_off.resize(count);
+    lay->tab_off.resize(count);
+    size_t off = 0;
+    for (int q = 0; q < count; ++q) {
+        if (probs[q].dtype != probs[0].dtype) return fail(SWEPT_EINVAL, "all problems of a batch share one dtype");
+        swept_tuning t{tunes ? tunes[q].tile : 0, swept::kBatchWG};
+        const int rc = derive(&probs[q], &t, &(*d)[q]);
+        if (rc) return rc;
+        lay->buf1_off[q] = off;
+        off += align_up((*d)[q].state_bytes);
+        lay->tab_off[q] = off;
+        off += align_up(table_bytes((*d)[q]));
+    }
+    lay->args_off = off;
+    lay->total = off + align_up(sizeof(swept::PhaseArgs) * count);
+    return SWEPT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int swept_batch_workspace_bytes(const swept_problem* probs, const swept_tuning* tunes, int32_t count, size_t* bytes)
+{
+    if (!bytes) return fail(SWEPT_EINVAL, "bytes is NULL");
+    std::vector<Derived> d;
+    BatchLayout lay;
+    const int rc = batch_derive(probs, tunes, count, &d, &lay);
+    if (rc) return rc;
+    *bytes = lay.total;
+    return SWEPT_OK;
+}
+
+int swept_batch_init(swept_batch** ctx, const swept_problem* probs, const swept_tuning* tunes, void* const* d_states,
+                     int32_t count, void* d_work, size_t work_bytes, void* hip_stream)
+{
+    if (!ctx) return fail(SWEPT_EINVAL, "ctx is NULL");
+    *ctx = nullptr;
+    std::vector<Derived> d;
+    BatchLayout lay;
+    int rc = batch_derive(probs, tunes, count, &d, &lay);
+    if (rc) return rc;
+    if (!d_states || !d_work) return fail(SWEPT_EINVAL, "NULL state array or workspace");
+    for (int q = 0; q < count; ++q)
+        if (!d_states[q] || reinterpret_cast<uintptr_t>(d_states[q]) % 16)
+            return fail(SWEPT_EINVAL, "state %d is NULL or not 16-byte aligned", q);
+    if (reinterpret_cast<uintptr_t>(d_work) % 16) return fail(SWEPT_EINVAL, "workspace not 16-byte aligned");
+    if (work_bytes < lay.total) return fail(SWEPT_EWORKSPACE, "workspace %zu bytes < %zu needed", work_bytes, lay.total);
+    swept_batch* b = new (std::nothrow) swept_batch();
+    if (!b) return fail(SWEPT_EINVAL, "out of host memory");
+    b->count = count;
+    b->dtype = probs[0].dtype;
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    b->probs.assign(probs, probs + count);
+    b->d = d;
+    char* w = static_cast<char*>(d_work);
+    std::vector<swept::PhaseArgs> args(count);
+    std::vector<std::vector<swept::LevelEntry>> tabs(count);
+    for (int q = 0; q < count; ++q) {
+        b->states.push_back(d_states[q]);
+        b->buf1s.push_back(w + lay.buf1_off[q]);
+        b->lds = std::max(b->lds, d[q].lds_bytes);
+        tabs[q].resize(swept::level_table_entries(d[q].h));
+        build_level_table(d[q], tabs[q].data());
+        swept::PhaseArgs& a = args[q];
+        a = swept::PhaseArgs{};
+        a.buf0 = a.out0 = d_states[q];
+        a.buf1 = a.out1 = w + lay.buf1_off[q];
+        a.lvl0 = d_states[q];
+        a.N = probs[q].nx;
+        a.tile = d[q].tile;
+        a.h = d[q].h;
+        a.tiles = probs[q].nx / d[q].tile;
+        a.kind = probs[q].kind;
+        a.tab = reinterpret_cast<swept::LevelEntry*>(w + lay.tab_off[q]);
+        if (probs[q].kind == SWEPT_HEAT) {
+            a.p[0] = d[q].r;
+        } else {
+            a.p[0] = probs[q].gamma;
+            a.p[1] = 0.5 * probs[q].dt / d[q].dx;
+            a.p[2] = 0.5 * probs[q].dt / d[q].dy;
+            a.p[3] = probs[q].dt / d[q].dx;
+            a.p[4] = probs[q].dt / d[q].dy;
+        }
+    }
+    b->dev_args = reinterpret_cast<swept::PhaseArgs*>(w + lay.args_off);
+    hipError_t e = swept::set_batch_lds_limit(b->dtype, kLdsMax);
+    int bpc = 0, dev = 0, cus = 0;
+    if (e == hipSuccess) e = swept::batch_occupancy(b->dtype, b->lds, &bpc);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    for (int q = 0; q < count && e == hipSuccess; ++q)
+        e = hipMemcpyAsync(w + lay.tab_off[q], tabs[q].data(), table_bytes(d[q]), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->dev_args, args.data(), sizeof(swept::PhaseArgs) * count, hipMemcpyHostToDevice,
+                           b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        delete b;
+        return hip_fail(e, "batch init");
+    }
+    if (bpc < 1) {
+        delete b;
+        return fail(SWEPT_ESHAPE, "batch workgroup (%zu bytes of LDS) does not fit a compute unit", b->lds);
+    }
+    b->grid = bpc * cus;
+    *ctx = b;
+    return SWEPT_OK;
+}
+
+int swept_batch_advance(swept_batch* b, int64_t n_steps)
+{
+    if (!b) return fail(SWEPT_EINVAL, "ctx is NULL");
+    if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
+    if (n_steps == 0) return SWEPT_OK;
+    if (n_steps > (int64_t)1 << 28) return fail(SWEPT_EINVAL, "n_steps too large");
+    int nph = 0;
+    for (int q = 0; q < b->count; ++q) {
+        const int64_t L = n_steps * b->d[q].lps;
+        nph = std::max(nph, (int)(2 * ((L + b->d[q].h - 1) / b->d[q].h) + 1));
+    }
+    hipError_t e = swept::launch_batch(b->dtype, b->dev_args, b->count, nph, (long long)n_steps, b->grid, b->lds,
+                                       b->stream);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+    for (int q = 0; q < b->count; ++q) {
+        if ((n_steps * b->d[q].lps) & 1) {
+            e = hipMemcpyAsync(b->states[q], b->buf1s[q], b->d[q].state_bytes, hipMemcpyDeviceToDevice, b->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        }
+    }
+    return SWEPT_OK;
+}
+
+int swept_batch_query(const swept_batch* b, int32_t q, swept_info* info)
+{
+    if (!b || !info || q < 0 || q >= b->count) return fail(SWEPT_EINVAL, "bad argument");
+    const Derived& d = b->d[q];
+    info->nvar = d.nvar;
+    info->n = d.n;
+    info->levels_per_step = d.lps;
+    info->tile = d.tile;
+    info->h = d.h;
+    info->wg = d.wg;
+    info->r = d.r;
+    info->dx = d.dx;
+    info->dy = d.dy;
+    info->state_bytes = d.state_bytes;
+    info->lds_bytes = d.lds_bytes;
+    return SWEPT_OK;
+}
+
+int swept_batch_grid(const swept_batch* b, int32_t* grid)
+{
+    if (!b || !grid) return fail(SWEPT_EINVAL, "bad argument");
+    *grid = b->grid;
+    return SWEPT_OK;
+}
+
+int swept_batch_set_stream(swept_batch* b, void* hip_stream)
+{
+    if (!b) return fail(SWEPT_EINVAL, "ctx is NULL");
+    b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return SWEPT_OK;
+}
+
+int swept_batch_destroy(swept_batch* b)
+{
+    delete b;
     return SWEPT_OK;
 }
 

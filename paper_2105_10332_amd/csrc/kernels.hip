@@ -32,73 +32,7 @@ template <class S, typename T>
 __global__ void __launch_bounds__(S::MAXWG) swept_phase_kernel(PhaseArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* lds = reinterpret_cast<T*>(smem_raw);
-    constexpr int NVAR = S::NVAR, R = S::R;
-    const int b = a.tile, h = a.h, N = a.N, L = a.L;
-    const int W = b + 2 * R, P = W * W;
-    const size_t NN = (size_t)N * N;
-    const int tiles = a.tiles, t2 = tiles * tiles;
-
-    // instance decode: phase 2w -> Octahedron (w, w); phase 2w-1 -> Bridges (w, w-1) then (w-1, w)
-    int wx, wy, inst = blockIdx.x;
-    if ((a.phase & 1) == 0) {
-        wx = wy = a.phase >> 1;
-    } else {
-        const int w = (a.phase + 1) >> 1;
-        const int k = inst >= t2;
-        inst -= k * t2;
-        wx = k ? w - 1 : w;
-        wy = k ? w : w - 1;
-    }
-    const int jx = inst % tiles, jy = inst / tiles;
-    const int wmax = wx > wy ? wx : wy, wmin = wx < wy ? wx : wy;
-    const int lo = max(1, (wmax - 1) * h + 1);
-    const int hi = min(L, (wmin + 1) * h - 1);
-    if (lo > hi) return;
-
-    const int C = b / 2 + R;  // window centre (local): footprints are [C-hw, C+hw)
-    const int cx = jx * b + ((wx & 1) ? 0 : b / 2);
-    const int cy = jy * b + ((wy & 1) ? 0 : b / 2);
-    const int ox = cx - C, oy = cy - C;
-    T* g0 = reinterpret_cast<T*>(a.out0);
-    T* g1 = reinterpret_cast<T*>(a.out1);
-    const int BUF = NVAR * P;  // LDS values per level-parity buffer (address arithmetic keeps ds_* access)
-
-    const RingSrc<T> src{reinterpret_cast<const T*>(a.buf0), reinterpret_cast<const T*>(a.buf1),
-                         reinterpret_cast<const T*>(a.lvl0), nullptr, nullptr, false};
-    preload_rings<S, T>(lds, BUF, src, W, P, N, NN, ox, oy, wx, wy, lo, hi, h, C);
-    __syncthreads();
-
-    // level table of this shape type, indexed by the level within its window
-    const LevelEntry* tab;
-    int kbase;
-    if (wx == wy) {
-        tab = a.tab;
-        kbase = wx == 0 ? -h : (wx - 1) * h;  // the Up-Pyramid is the Octahedron's upper half
-    } else {
-        tab = a.tab + (wx > wy ? 2 * h : 3 * h);
-        kbase = (wmax - 1) * h;
-    }
-    for (int lvl = lo; lvl <= hi; ++lvl) {
-        const LevelEntry e = tab[lvl - kbase];
-        const bool has2 = lvl + 2 <= hi;
-        const int hx2 = has2 ? e.hx2 : 0, hy2 = has2 ? e.hy2 : 0;
-        const T* prev = lds + ((lvl - 1) & 1) * BUF;
-        T* cur = lds + (lvl & 1) * BUF;
-        T* gout = (lvl & 1) ? g1 : g0;
-        if constexpr (NVAR == 1) {
-            heat_level<T>(prev, cur, gout, W, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
-        } else {
-            T* pbuf = lds + 2 * BUF;
-            T* fbuf = pbuf + P;
-            const int FS = (b + 1) * b;
-            const bool second = (lvl & 1) == 0;
-            const SweptStore<T, NVAR> st{gout, NN, N, ox, oy, C, hx2, hy2};
-            euler_level<T>(prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second, (T)a.p[0],
-                           (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]), st);
-        }
-        __syncthreads();
-    }
+    phase_instance<S, T>(a, blockIdx.x, smem_raw);
 }
 
 // ------------------------------------------------------------ Standard steps

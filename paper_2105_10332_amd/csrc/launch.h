@@ -39,6 +39,7 @@ struct PhaseArgs {
     void* lam1;
     double* partials;  // adjoint only: one pairing partial sum per workgroup
     int shift;         // adjoint only: 1 = the reversed sweep runs on the other tiling
+    int kind;          // batch only: 0 heat, 1 Euler (single-problem launches pick the kernel by template)
     int N;        // cells per side
     int tile;     // b
     int h;        // b / (2n)
@@ -67,6 +68,14 @@ hipError_t set_adjoint_lds_limit(int dtype, size_t lds);
 hipError_t launch_adjoint_phase(int dtype, const PhaseArgs& a, int pk_max, int wg, size_t lds, hipStream_t st);
 hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const void* Tm, int N, double r,
                                double* partials, int nblocks, hipStream_t st);
+// Batched persistent launch: every problem's phases in one cooperative
+// kernel, global phase g running phase g of every problem that has one.
+constexpr int kBatchMax = 256;
+constexpr int kBatchWG = 256;
+hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu);
+hipError_t set_batch_lds_limit(int dtype, size_t lds);
+hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphase_max, long long n_steps, int grid,
+                        size_t lds, hipStream_t st);
 hipError_t launch_combine(const double* partials, int nparts, double* out, hipStream_t st);
 hipError_t launch_plane_sums(int dtype, const void* x, int nvar, size_t NN, double* partials, int nparts,
                              double* out, hipStream_t st);

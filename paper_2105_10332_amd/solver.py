@@ -122,6 +122,56 @@ class SweptSolver:
             pass
 
 
+class SweptBatch:
+    """Many problems (heat (N, N) and Euler (4, N, N) tensors, one dtype) advanced
+    together by one persistent launch per swept_batch_advance (see swept.h).
+
+    items: list of (kind, state, dt, length, alpha, gamma, tile)."""
+
+    def __init__(self, items):
+        n = len(items)
+        self.states = [it[1] for it in items]
+        probs = (Problem * n)()
+        tunes = (Tuning * n)()
+        for q, (kind, st, dt, length, alpha, gamma, tile) in enumerate(items):
+            probs[q] = make_problem(kind, st.shape[-1], st.dtype, dt, length, alpha, gamma)
+            tunes[q] = Tuning(int(tile), 0)
+        out = ctypes.c_size_t(0)
+        check(lib().swept_batch_workspace_bytes(probs, tunes, n, ctypes.byref(out)))
+        self.work = torch.empty(out.value, dtype=torch.uint8, device=self.states[0].device)
+        ptrs = (ctypes.c_void_p * n)(*[_dev_ptr(st).value for st in self.states])
+        self._ctx = ctypes.c_void_p(0)
+        check(lib().swept_batch_init(ctypes.byref(self._ctx), probs, tunes, ptrs, n, _dev_ptr(self.work),
+                                     out.value, _stream_ptr()))
+        self.count = n
+
+    def swept_batch_advance(self, n_steps: int):
+        check(lib().swept_batch_set_stream(self._ctx, _stream_ptr()))
+        check(lib().swept_batch_advance(self._ctx, int(n_steps)))
+
+    def info(self, q: int) -> Info:
+        inf = Info()
+        check(lib().swept_batch_query(self._ctx, q, ctypes.byref(inf)))
+        return inf
+
+    @property
+    def grid(self) -> int:
+        g = ctypes.c_int32(0)
+        check(lib().swept_batch_grid(self._ctx, ctypes.byref(g)))
+        return g.value
+
+    def close(self):
+        if self._ctx:
+            lib().swept_batch_destroy(self._ctx)
+            self._ctx = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class SweptHeatAdvance(torch.autograd.Function):
     """T^M = swept heat advance of T^0 by n_steps with diffusivity alpha, differentiable
     in T^0 and alpha through the hand-written swept adjoint (swept_adjoint).
@@ -167,4 +217,4 @@ def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 
     return out.value
 
 
-__all__ = ["SweptSolver", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT", "EULER", "_lib"]
+__all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT", "EULER", "_lib"]

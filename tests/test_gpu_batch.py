@@ -1,0 +1,64 @@
+"""GPU: the batched persistent launch equals each problem's own swept advance bit for bit."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_10332_amd import problems
+from paper_2105_10332_amd.solver import EULER, HEAT, SweptBatch, SweptSolver
+
+from gpu_helpers import DEV, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+def _items(dtype, spec):
+    items = []
+    for kind, n, tile, par in spec:
+        if kind == HEAT:
+            x = torch.tensor(problems.heat_fourier_modes(n, seed=n), dtype=dtype, device=DEV)
+            items.append((HEAT, x, par / n / n, 1.0, 1.0, 1.4, tile))
+        else:
+            q0 = problems.shu_vortex(n, eps=par)
+            dt = oracle.cfl_dt(q0, 10 / n, 10 / n, 1.4, 0.4)
+            items.append((EULER, torch.tensor(q0, dtype=dtype, device=DEV), dt, 10.0, 1.0, 1.4, tile))
+    return items
+
+
+SPEC = [(HEAT, 64, 16, 0.2), (HEAT, 96, 32, 0.05), (HEAT, 128, 64, 0.24), (EULER, 64, 16, 5.0),
+        (EULER, 96, 32, 2.5), (HEAT, 160, 32, 0.12), (EULER, 48, 8, 1.0)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("steps", [1, 13, 40])
+def test_batch_equals_standalone(dtype, steps):
+    items = _items(dtype, SPEC)
+    refs = []
+    for kind, x, dt, length, alpha, gamma, tile in items:
+        y = x.clone()
+        s = SweptSolver(kind, y, dt=dt, length=length, alpha=alpha, gamma=gamma, tile=tile)
+        s.swept_advance(steps)
+        refs.append((y, s))
+    b = SweptBatch(items)
+    b.swept_batch_advance(steps)
+    torch.cuda.synchronize()
+    for q, ((kind, x, *_), (y, _)) in enumerate(zip(items, refs)):
+        assert torch.equal(x, y), (q, SPEC[q])
+    assert b.grid >= 256
+
+
+def test_batch_vs_oracle_and_twice():
+    """Two consecutive batch advances (state carried over) against the oracle."""
+    items = _items(torch.float64, SPEC[:4])
+    init = [it[1].cpu().numpy().copy() for it in items]
+    b = SweptBatch(items)
+    b.swept_batch_advance(9)
+    b.swept_batch_advance(14)
+    torch.cuda.synchronize()
+    for q, (kind, x, dt, length, alpha, gamma, tile) in enumerate(items):
+        n = x.shape[-1]
+        if kind == HEAT:
+            ref = oracle.heat_run(init[q], b.info(q).r, 23)
+        else:
+            ref = oracle.euler_run(init[q], dt, 10 / n, 10 / n, 1.4, 23)
+        assert rel_err(x.cpu().numpy(), ref) <= 1e-10
