@@ -100,6 +100,7 @@ __device__ __forceinline__ int ring_parities(int wx, int wy, int lo, int hi, int
 
 // Sources of the up-front load: level-parity buffers g0/g1, the level-0
 // state (normally g0 itself) and, for the adjoint, the Bridges' buffers.
+// Kept as plain pointers (a struct of them ends up indexed in scratch).
 template <typename T>
 struct RingSrc {
     const T* g0;
@@ -118,6 +119,12 @@ __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>&
                                               int ox, int oy, int wx, int wy, int lo, int hi, int h, int C)
 {
     constexpr int NVAR = S::NVAR, KB = 4;
+    const T* __restrict__ g0 = src.g0;
+    const T* __restrict__ g1 = src.g1;
+    const T* __restrict__ z0 = src.lvl0;
+    const T* __restrict__ q0 = src.q0;
+    const T* __restrict__ q1 = src.q1;
+    const bool owner_q = src.owner_q;
     const int cnt = W * W;
     const float invW = 1.0f / (float)W;
     for (int base = 0; base < cnt; base += KB * (int)blockDim.x) {
@@ -130,18 +137,29 @@ __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>&
             li[k] = i;
             if (i < cnt) {
                 const int ly = qdiv(i, invW), lx = i - ly * W;
-                pm[k] = ring_parities<S::R, S::TWO_STAGE>(wx, wy, lo, hi, h, W - 2 * S::R, C, lx, ly, src.owner_q);
+                pm[k] = ring_parities<S::R, S::TWO_STAGE>(wx, wy, lo, hi, h, W - 2 * S::R, C, lx, ly, owner_q);
                 if (pm[k] & 3) {
                     const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
                     if (pm[k] & 1) {
-                        const T* g = (pm[k] & RING_LEVEL0) ? src.lvl0 : ((pm[k] & RING_Q0) ? src.q0 : src.g0);
+                        if (pm[k] & RING_LEVEL0) {
 #pragma unroll
-                        for (int c = 0; c < NVAR; ++c) v[k][0][c] = g[c * NN + gi];
+                            for (int c = 0; c < NVAR; ++c) v[k][0][c] = z0[c * NN + gi];
+                        } else if (pm[k] & RING_Q0) {
+#pragma unroll
+                            for (int c = 0; c < NVAR; ++c) v[k][0][c] = q0[c * NN + gi];
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < NVAR; ++c) v[k][0][c] = g0[c * NN + gi];
+                        }
                     }
                     if (pm[k] & 2) {
-                        const T* g = (pm[k] & RING_Q1) ? src.q1 : src.g1;
+                        if (pm[k] & RING_Q1) {
 #pragma unroll
-                        for (int c = 0; c < NVAR; ++c) v[k][1][c] = g[c * NN + gi];
+                            for (int c = 0; c < NVAR; ++c) v[k][1][c] = q1[c * NN + gi];
+                        } else {
+#pragma unroll
+                            for (int c = 0; c < NVAR; ++c) v[k][1][c] = g1[c * NN + gi];
+                        }
                     }
                 }
             }
