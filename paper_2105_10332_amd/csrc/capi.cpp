@@ -30,6 +30,7 @@ int fail(int code, const char* fmt, ...)
 
 int hip_fail(hipError_t e, const char* what)
 {
+    (void)hipGetLastError();  // reported here: do not let it resurface at the caller's next HIP call
     return fail(SWEPT_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
@@ -64,9 +65,9 @@ bool tile_ok(int N, int tile, int n, int nvar, size_t scalar)
 
 int default_tile(const swept_problem* p, int n, int nvar, size_t scalar)
 {
-    static const int heat_order[] = {32, 64, 16, 8, 0};
+    static const int heat_order[] = {64, 32, 16, 8, 0};
     static const int e64_order[] = {16, 32, 8, 0};
-    static const int e32_order[] = {32, 16, 64, 8, 0};
+    static const int e32_order[] = {16, 32, 8, 0};
     const int* order = p->kind == SWEPT_HEAT ? heat_order : (p->dtype == SWEPT_F64 ? e64_order : e32_order);
     for (int k = 0; order[k]; ++k)
         if (tile_ok(p->nx, order[k], n, nvar, scalar)) return order[k];
@@ -698,7 +699,13 @@ int swept_batch_init(swept_batch** ctx, const swept_problem* probs, const swept_
         }
     }
     b->dev_args = reinterpret_cast<swept::PhaseArgs*>(w + lay.args_off);
-    hipError_t e = swept::set_batch_lds_limit(b->dtype, kLdsMax);
+    // the batch kernel also has a small static LDS array (its per-phase item prefix)
+    const size_t dyn_max = kLdsMax - swept::kBatchStaticLds;
+    if (b->lds > dyn_max) {
+        delete b;
+        return fail(SWEPT_ESHAPE, "batch needs %zu bytes of LDS per workgroup (max %zu)", b->lds, dyn_max);
+    }
+    hipError_t e = swept::set_batch_lds_limit(b->dtype, dyn_max);
     int bpc = 0, dev = 0, cus = 0;
     if (e == hipSuccess) e = swept::batch_occupancy(b->dtype, b->lds, &bpc);
     if (e == hipSuccess) e = hipGetDevice(&dev);

@@ -72,6 +72,7 @@ hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const voi
 // kernel, global phase g running phase g of every problem that has one.
 constexpr int kBatchMax = 256;
 constexpr int kBatchWG = 256;
+constexpr size_t kBatchStaticLds = 2048;  // >= sizeof(int) * (kBatchMax + 1), the kernel's static array
 hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu);
 hipError_t set_batch_lds_limit(int dtype, size_t lds);
 hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphase_max, long long n_steps, int grid,

@@ -74,7 +74,7 @@ def candidates(kind: str, dtype: str, n: int):
 
 
 def default_tile(kind: str, dtype: str, n: int) -> int:
-    order = {"heat": (32, 64, 16, 8), "euler": (16, 32, 8) if dtype == "f64" else (32, 16, 64, 8)}[kind]
+    order = {"heat": (64, 32, 16, 8), "euler": (16, 32, 8)}[kind]
     valid = {b for b, _ in candidates(kind, dtype, n)}
     for b in order:
         if b in valid:
