@@ -34,6 +34,29 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB/s"
 
+# HBM bytes per launch of the swept phase kernel from two rocprofv3 --pmc passes (FETCH_SIZE x 2.0,
+# WRITE_SIZE x 1.0: the factors a plain copy of known size reads), keyed by workload and launch
+# shape, valid only for the kernel sources whose hash is recorded with it (null otherwise).
+MEASURED_TRAFFIC = {
+    ("heat", "f64", 4096, 64, 512, 1000): (630.6e6, "2af9733d8432a18f"),
+}
+KERNEL_SOURCES = ("scheme.h", "device_common.h", "kernels.hip", "launch.h")
+
+
+def kernel_hash():
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2105_10332_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(key):
+    rec = MEASURED_TRAFFIC.get(key)
+    return rec[0] if rec and rec[1] == kernel_hash() else None
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -155,6 +178,7 @@ def run_heat(args):
     out = base_record(args, rate, "cell-updates/s", sec, dt_name, cfg)
     out["effective_GBps"] = 2 * S * updates / sec / 1e9
     out["roofline"] = roofline(plan, S, 1, plan["launches"] * args.steps, sec, "swept_phase_kernel<HeatS>")
+    out["roofline"]["traffic"] = measured_traffic(("heat", dt_name, n, tile, solver.info.wg, M))
     if not args.no_standard:
         st = torch.tensor(T0, dtype=tdt, device="cuda")
         ss = SweptSolver(HEAT, st, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile)
