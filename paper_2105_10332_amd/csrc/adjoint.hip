@@ -51,13 +51,14 @@ __device__ __forceinline__ void heat_level_pack(const T* __restrict__ prev, T* _
 
 // Reverse level: lambda on F(k) from lambda at k-1 (`prev`), the pairing
 // (L lambda^{k-1}) * T at each cell accumulated in double, and the
-// top-two-levels store of lambda.  T comes from the packed store (row-major
-// over the same footprint) or, for the cycle's level 0, from global memory.
-template <typename T>
+// top-two-levels store of lambda.  T comes from the packed store in LDS
+// (row-major over the same footprint) or, for the cycle's level 0
+// (T_GLOBAL), from the checkpoint in global memory; the two are separate
+// instantiations so that each is read with its own load instructions.
+template <typename T, bool T_GLOBAL>
 __device__ __forceinline__ double lambda_level(const T* __restrict__ prev, T* __restrict__ cur,
-                                               T* __restrict__ gout, const T* __restrict__ tpk,
-                                               const T* __restrict__ tglob, int W, int C, const LevelEntry& e,
-                                               int hx2, int hy2, int ox, int oy, int N, T r)
+                                               T* __restrict__ gout, const T* __restrict__ tsrc, int W, int C,
+                                               const LevelEntry& e, int hx2, int hy2, int ox, int oy, int N, T r)
 {
     const int fw = e.fw, cells = fw * e.fh;
     double acc = 0.0;
@@ -72,7 +73,7 @@ __device__ __forceinline__ double lambda_level(const T* __restrict__ prev, T* __
         const T v = (c + r * dxx) + r * dyy;  // the heat update (scheme.h) with its Laplacian kept
         cur[li] = v;
         const int gx = wrapi(ox + lx, N), gy = wrapi(oy + ly, N);
-        const T tv = tpk ? tpk[i] : tglob[(size_t)gy * N + gx];
+        const T tv = T_GLOBAL ? tsrc[(size_t)gy * N + gx] : tsrc[i];
         acc += ((double)dxx + (double)dyy) * (double)tv;
         const int dx = lx - C, dy = ly - C;
         if (!((dx >= -hx2) && (dx < hx2) && (dy >= -hy2) && (dy < hy2))) gout[(size_t)gy * N + gx] = v;
@@ -94,24 +95,28 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 }
 
 // Byte layout of the adjoint workgroup's LDS (shared by host and device).
+// The forward recompute's parity windows, then the lambda parity windows,
+// then the reduction scratch use one region in turn (each is dead before the
+// next is written); the packed forward levels and their offsets follow.
 struct AdjLds {
-    size_t pk, offs, red, total;
+    size_t pk, offs, total;
 };
 __host__ __device__ inline AdjLds adjoint_lds_layout(size_t scalar, int tile, int pk_max, int wg)
 {
     const size_t W = tile + 2;
     const int h = tile / 2;
+    const size_t win = scalar * 2 * W * W, red = sizeof(double) * wg;
     AdjLds l;
-    l.pk = scalar * 4 * W * W;
+    l.pk = ((win > red ? win : red) + 15) / 16 * 16;
     l.offs = (l.pk + scalar * pk_max + 15) / 16 * 16;
-    l.red = (l.offs + sizeof(int) * (2 * h + 2) + 15) / 16 * 16;
-    l.total = l.red + sizeof(double) * wg;
+    l.total = l.offs + sizeof(int) * (2 * h + 2);
     return l;
 }
 
 // One reverse phase (k-time phase 0, 1 or 2) of a full cycle of h levels.
-// LDS: forward parity windows (2 W^2), lambda parity windows (2 W^2), the
-// packed forward levels (pk_max values) and the reduction scratch.
+// LDS: one region of two parity windows (forward T, then lambda, then the
+// reduction scratch), the packed forward levels (pk_max values) and their
+// offsets.
 template <typename T>
 __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk_max)
 {
@@ -122,10 +127,10 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     const int tiles = a.tiles, t2 = tiles * tiles;
     const AdjLds lay = adjoint_lds_layout(sizeof(T), b, pk_max, blockDim.x);
     T* tpar = reinterpret_cast<T*>(smem_raw);
-    T* lpar = tpar + 2 * P;
+    T* lpar = tpar;  // the forward windows are dead once every level is packed
     T* pk = reinterpret_cast<T*>(smem_raw + lay.pk);
     int* offs = reinterpret_cast<int*>(smem_raw + lay.offs);  // packed offset of each forward level
-    double* red = reinterpret_cast<double*>(smem_raw + lay.red);
+    double* red = reinterpret_cast<double*>(smem_raw);  // after the last lambda level
 
     // k-time shape of this workgroup (same decode as the forward phases)
     int kx, ky, inst = blockIdx.x;
@@ -206,9 +211,14 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
         const bool has2 = k + 2 <= khi;
         const int hx2 = has2 ? e.hx2 : 0, hy2 = has2 ? e.hy2 : 0;
         const int j = h - k;
-        const T* tp = j >= 1 ? pk + offs[j] : nullptr;
-        acc += lambda_level<T>(lpar + ((k - 1) & 1) * P, lpar + (k & 1) * P, (k & 1) ? l1 : l0, tp,
-                               reinterpret_cast<const T*>(a.lvl0), W, C, e, hx2, hy2, ox, oy, N, r);
+        T* lprev = lpar + ((k - 1) & 1) * P;
+        T* lcur = lpar + (k & 1) * P;
+        T* gout = (k & 1) ? l1 : l0;
+        if (j >= 1)
+            acc += lambda_level<T, false>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N, r);
+        else
+            acc += lambda_level<T, true>(lprev, lcur, gout, reinterpret_cast<const T*>(a.lvl0), W, C, e, hx2, hy2,
+                                         ox, oy, N, r);
         __syncthreads();
     }
     const double tot = block_sum(acc, red);

@@ -143,6 +143,7 @@ struct TapePlan {
 };
 
 constexpr int kStdAdjBlocks = 1024;
+constexpr int kAdjCombine = 512;  // first-stage blocks of the pairing sum (fixed chunks, fixed order)
 
 int tape_plan(const Derived& d, int nx, int64_t n_steps, TapePlan* t)
 {
@@ -158,7 +159,7 @@ int tape_plan(const Derived& d, int nx, int64_t n_steps, TapePlan* t)
     t->stash_off = t->pairs_off + 6 * S;  // P0 P1 Q0 Q1 L0 L1
     t->part_off = t->stash_off + S * (size_t)t->rem;
     t->nparts = t->cycles * 4 * (int64_t)tiles * tiles + t->rem * kStdAdjBlocks;
-    t->total = t->part_off + align_up(sizeof(double) * (size_t)(t->nparts + 1));
+    t->total = t->part_off + align_up(sizeof(double) * (size_t)(t->nparts + 1 + kAdjCombine));
     return SWEPT_OK;
 }
 
@@ -498,7 +499,9 @@ int swept_adjoint(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes
         }
     }
     e = hipMemcpyAsync(d_gT0, La, SB, hipMemcpyDeviceToDevice, st);
-    if (e == hipSuccess) e = swept::launch_combine(parts, (int)pslot, parts + t.nparts, st);
+    if (e == hipSuccess)
+        e = swept::launch_plane_sums(0, parts, 1, (size_t)pslot, parts + t.nparts + 1, kAdjCombine, parts + t.nparts,
+                                     st);
     double dJdr = 0.0;
     if (e == hipSuccess) e = hipMemcpyAsync(&dJdr, parts + t.nparts, sizeof(double), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
