@@ -198,7 +198,6 @@ def run_euler(args):
     import numpy as np
     import torch
 
-    import oracle
     from paper_2105_10332_amd import geometry, problems, tune
     from paper_2105_10332_amd.solver import EULER, SweptSolver, swept_cfl_dt
 
@@ -283,25 +282,24 @@ def run_adjoint(args):
 def run_batch(args):
     import torch
 
-    import oracle
     from paper_2105_10332_amd import problems, tune
-    from paper_2105_10332_amd.solver import EULER, HEAT, SweptBatch, SweptSolver
+    from paper_2105_10332_amd.solver import EULER, HEAT, SweptBatch, SweptSolver, swept_cfl_dt
 
     dt_name = args.dtype or "f32"
     tdt = torch.float64 if dt_name == "f64" else torch.float32
     M = args.advance_steps or 200
     items, cells = [], 0
-    for it in problems.batch_ensemble():
+    ens = problems.batch_ensemble()
+    tiles = tune.batch_tiles([(it.kind, it.n) for it in ens], dt_name)
+    for it, tile in zip(ens, tiles):
         n = it.n
         if it.kind == "heat":
             x = torch.tensor(problems.heat_fourier_modes(n, seed=it.seed), dtype=tdt, device="cuda")
-            tile = tune.best_tile("heat", dt_name, n)
             items.append((HEAT, x, it.r / n / n, 1.0, 1.0, 1.4, tile))
         else:
-            q0 = problems.shu_vortex(n, eps=it.eps)
-            dt = oracle.cfl_dt(q0, 10 / n, 10 / n, 1.4, 0.4)
-            tile = tune.best_tile("euler", dt_name, n)
-            items.append((EULER, torch.tensor(q0, dtype=tdt, device="cuda"), dt, 10.0, 1.0, 1.4, tile))
+            q0 = torch.tensor(problems.shu_vortex(n, eps=it.eps), device="cuda")
+            dt = swept_cfl_dt(q0, 10.0, 0.4)
+            items.append((EULER, q0.to(tdt), dt, 10.0, 1.0, 1.4, tile))
         cells += n * n * M
     init = [it[1].clone() for it in items]
     b = SweptBatch(items)
@@ -314,7 +312,7 @@ def run_batch(args):
     for _ in range(args.warmup):
         one()
     sec, wall = timed(one, args.steps)
-    # the same problems one after another with their own swept advance (reference rate)
+    # the same problems (same tiles) one after another, each with its own swept advance (reference rate)
     solvers = [SweptSolver(k, x, dt=dt, length=L, alpha=a, gamma=g, tile=t) for (k, x, dt, L, a, g, t) in items]
 
     def seq():
@@ -325,7 +323,9 @@ def run_batch(args):
     ssec, _ = timed(seq, 1)
     cfg = {"workload": f"batch of 48 heat (edges 128-1024, r 0.05-0.24) + 16 Euler vortex (edges 256-1024, "
                        f"eps 1-5) problems, {M} steps each, one persistent launch; grid {b.grid} workgroups",
-           "problems": len(items), "grid": b.grid}
+           "problems": len(items), "grid": b.grid,
+           "tiles": {"heat": sorted(set(t for it, t in zip(ens, tiles) if it.kind == "heat")),
+                     "euler": sorted(set(t for it, t in zip(ens, tiles) if it.kind == "euler"))}}
     out = base_record(args, cells * args.steps / sec, "cell-updates/s", sec, dt_name, cfg)
     out["sequential_swept"] = {"value": cells / ssec, "unit": "cell-updates/s", "ms": ssec * 1e3}
     out["wall_s"] = wall

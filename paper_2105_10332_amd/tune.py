@@ -137,3 +137,89 @@ def tune(kind: str, dtype: str, n: int, steps: int = 0, reps: int = 2, save: boo
                                    "all": [[r[1], r[2], round(r[0], 4)] for r in results]}
         save_cache(c)
     return b, wg, results
+
+
+# ---------------------------------------------------------------- batches
+# One persistent launch runs every problem's phases in lockstep global
+# phases, so a batch has its own best tiles: the deepest tile that fits a
+# problem cuts its phase count, while the largest LDS window sets how many
+# workgroups share a compute unit.  The batch tuner times a preferred tile
+# per problem kind (each problem takes the largest valid tile not above it).
+
+BATCH_PREFS = {"heat": (64, 32, 16), "euler": (32, 16)}
+BATCH_DEFAULT = {"heat": 64, "euler": 32}
+
+
+def _batch_key(specs, dtype: str, arch: str | None = None) -> str:
+    import hashlib
+
+    sig = hashlib.sha256(repr(sorted((k, int(n)) for k, n in specs)).encode()).hexdigest()[:12]
+    return f"batch/{dtype}/{len(specs)}x{sig}/{arch or _arch()}"
+
+
+def tile_at_most(kind: str, dtype: str, n: int, pref: int) -> int:
+    valid = sorted({b for b, _ in candidates(kind, dtype, n)})
+    below = [b for b in valid if b <= pref]
+    return below[-1] if below else (valid[0] if valid else 0)
+
+
+def batch_tiles(specs, dtype: str, prefs: dict | None = None):
+    """Tile per problem of a batch given as [(kind, n), ...]: from the batch cache entry
+    for this ensemble if there is one, else the batch defaults."""
+    if prefs is None:
+        e = load_cache().get(_batch_key(specs, dtype))
+        prefs = {"heat": int(e["heat"]), "euler": int(e["euler"])} if e else BATCH_DEFAULT
+    return [tile_at_most(k, dtype, n, prefs[k]) for k, n in specs]
+
+
+def tune_batch(specs, dtype: str, steps: int = 64, reps: int = 2, save: bool = True, verbose: bool = False):
+    """Time the batch for every pair of preferred tiles and cache the fastest."""
+    import itertools
+
+    import torch
+
+    from . import problems
+    from .solver import EULER, HEAT, SweptBatch
+
+    dev = torch.device("cuda", 0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    states = []
+    for k, n in specs:
+        if k == "heat":
+            states.append(torch.tensor(problems.heat_fourier_modes(n), dtype=tdt, device=dev))
+        else:
+            states.append(torch.tensor(problems.shu_vortex(n), dtype=tdt, device=dev))
+    results = []
+    for hp, ep in itertools.product(BATCH_PREFS["heat"], BATCH_PREFS["euler"]):
+        tiles = batch_tiles(specs, dtype, {"heat": hp, "euler": ep})
+        items = []
+        for (k, n), x, b in zip(specs, states, tiles):
+            if k == "heat":
+                items.append((HEAT, x.clone(), 0.2 / n / n, 1.0, 1.0, 1.4, b))
+            else:
+                items.append((EULER, x.clone(), 0.4 * (10.0 / n) / 6.0, 10.0, 1.0, 1.4, b))
+        try:
+            bt = SweptBatch(items)
+        except Exception:  # e.g. the largest window does not fit: not a candidate
+            continue
+        bt.swept_batch_advance(steps)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            bt.swept_batch_advance(steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        results.append((ms, hp, ep))
+        if verbose:
+            print(f"tune batch {dtype}: heat <= {hp}, euler <= {ep}: {ms:.3f} ms", flush=True)
+        bt.close()
+    results.sort()
+    ms, hp, ep = results[0]
+    if save:
+        c = load_cache()
+        c[_batch_key(specs, dtype)] = {"heat": hp, "euler": ep, "ms": ms, "steps": steps,
+                                       "all": [[r[1], r[2], round(r[0], 4)] for r in results]}
+        save_cache(c)
+    return {"heat": hp, "euler": ep}, results
