@@ -38,7 +38,7 @@ METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB
 # WRITE_SIZE x 1.0: the factors a plain copy of known size reads), keyed by workload and launch
 # shape, valid only for the kernel sources whose hash is recorded with it (null otherwise).
 MEASURED_TRAFFIC = {
-    ("heat", "f64", 4096, 64, 512, 1000): (630.6e6, "2af9733d8432a18f"),
+    ("heat", "f64", 4096, 64, 512, 1000): (630.7e6, "d0c88e1fcea8bb58"),
 }
 KERNEL_SOURCES = ("scheme.h", "device_common.h", "kernels.hip", "launch.h")
 
@@ -71,6 +71,8 @@ def parse():
     ap.add_argument("--advance-steps", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-standard", action="store_true")
+    ap.add_argument("--copy-reference", action="store_true",
+                    help="only run a plain device copy of the C2 state size (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     return ap.parse_args()
 
 
@@ -332,12 +334,28 @@ def run_batch(args):
     return out
 
 
+def copy_reference(n: int = 4096, reps: int = 3):
+    """A plain device-to-device copy of one n x n FP64 state, reps times: the known-size
+    traffic that scales the HBM counters of the profiles."""
+    import torch
+
+    x = torch.ones(n * n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(reps):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_reference_bytes_each_way": x.numel() * 8, "copies": reps}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py measures one GPU (the swept path here is single-device); got --gpus {args.gpus}",
               file=sys.stderr)
         sys.exit(2)
+    if args.copy_reference:
+        copy_reference()
+        return
     fn = {"heat": run_heat, "euler": run_euler, "adjoint": run_adjoint, "batch": run_batch}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 

@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
         const RingSrc<T> src{reinterpret_cast<const T*>(a.buf0), reinterpret_cast<const T*>(a.buf1),
                              reinterpret_cast<const T*>(a.lvl0), reinterpret_cast<const T*>(a.q0),
                              reinterpret_cast<const T*>(a.q1), fx == 1 && fy == 1};
-        preload_rings<HeatS, T>(tpar, P, src, W, P, N, NN, ox, oy, fx, fy, flo, fhi, h, C);
+        preload_rings<HeatS, T>(tpar, P, src, W, P, W, N, NN, ox, oy, fx, fy, flo, fhi, h, C);
     }
     __syncthreads();
     for (int j = flo; j <= fhi; ++j) {
@@ -191,7 +191,7 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     {
         const RingSrc<T> src{reinterpret_cast<const T*>(a.lam0), reinterpret_cast<const T*>(a.lam1),
                              reinterpret_cast<const T*>(a.lam0), nullptr, nullptr, false};
-        preload_rings<HeatS, T>(lpar, P, src, W, P, N, NN, ox, oy, kx, ky, klo, khi, h, C);
+        preload_rings<HeatS, T>(lpar, P, src, W, P, W, N, NN, ox, oy, kx, ky, klo, khi, h, C);
     }
     const LevelEntry* ktab;
     int kkbase;

@@ -52,7 +52,7 @@ size_t phase_lds(int nvar, int n, int tile, size_t scalar)
 {
     if (nvar == 1) {
         const size_t W = (size_t)tile + 2 * n;
-        return 2 * W * W * scalar;
+        return 2 * W * (W + swept::kHeatPad) * scalar;
     }
     return swept::euler_phase_lds(scalar == 8 ? 0 : 1, tile);
 }

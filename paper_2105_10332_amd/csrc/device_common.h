@@ -111,11 +111,12 @@ struct RingSrc {
     bool owner_q;
 };
 
-// Up-front load of every ring of the shape: a strided pass over the window,
-// KB cells per thread per batch with all their loads issued before any LDS
-// write, so the batch costs one memory latency.
+// Up-front load of every ring of the shape: a strided pass over the W x W
+// window (LDS row pitch PITCH), KB cells per thread per batch with all their
+// loads issued before any LDS write, so the batch costs one memory latency.
 template <class S, typename T>
-__device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>& src, int W, int P, int N, size_t NN,
+__device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>& src, int W, int P, int PITCH, int N,
+                                              size_t NN,
                                               int ox, int oy, int wx, int wy, int lo, int hi, int h, int C)
 {
     constexpr int NVAR = S::NVAR, KB = 4;
@@ -137,6 +138,7 @@ __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>&
             li[k] = i;
             if (i < cnt) {
                 const int ly = qdiv(i, invW), lx = i - ly * W;
+                li[k] = ly * PITCH + lx;
                 pm[k] = ring_parities<S::R, S::TWO_STAGE>(wx, wy, lo, hi, h, W - 2 * S::R, C, lx, ly, owner_q);
                 if (pm[k] & 3) {
                     const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
@@ -302,8 +304,9 @@ __host__ __device__ inline size_t euler_lds_values(int W, int FS) { return (size
 // rows of them (R from the level table, so the footprint spreads over the
 // whole workgroup), keeping the vertical neighbours in registers: per row
 // two paired LDS reads (the next row of both columns; the outer left/right
-// neighbours) and one paired LDS write for two cell-updates.  Cells outside
-// F(l+2) (half-widths hx2, hy2) also go to the level's global buffer.
+// neighbours) and one paired LDS write for two cell-updates (W here is the
+// LDS row pitch).  Cells outside F(l+2) (half-widths hx2, hy2) also go to
+// the level's global buffer.
 template <typename T>
 __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ gout,
                                            int W, int C, const LevelEntry& e, int hx2, int hy2, int ox, int oy,
@@ -353,7 +356,9 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
     T* lds = reinterpret_cast<T*>(smem_raw);
     constexpr int NVAR = S::NVAR, R = S::R;
     const int b = a.tile, h = a.h, N = a.N, L = a.L;
-    const int W = b + 2 * R, P = W * W;
+    // heat pads its LDS rows by one value (fewer bank conflicts between the
+    // rows a wave touches at once); Euler keeps the pitch W
+    const int W = b + 2 * R, PITCH = W + (NVAR == 1 ? kHeatPad : 0), P = PITCH * W;
     const size_t NN = (size_t)N * N;
     const int tiles = a.tiles, t2 = tiles * tiles;
 
@@ -384,7 +389,7 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
 
     const RingSrc<T> src{reinterpret_cast<const T*>(a.buf0), reinterpret_cast<const T*>(a.buf1),
                          reinterpret_cast<const T*>(a.lvl0), nullptr, nullptr, false};
-    preload_rings<S, T>(lds, BUF, src, W, P, N, NN, ox, oy, wx, wy, lo, hi, h, C);
+    preload_rings<S, T>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C);
     __syncthreads();
 
     // level table of this shape type, indexed by the level within its window
@@ -405,7 +410,7 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         T* cur = lds + (lvl & 1) * BUF;
         T* gout = (lvl & 1) ? g1 : g0;
         if constexpr (NVAR == 1) {
-            heat_level<T>(prev, cur, gout, W, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
+            heat_level<T>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
         } else {
             T* pbuf = lds + 2 * BUF;
             T* fbuf = pbuf + P;

@@ -14,6 +14,9 @@ namespace swept {
 // the exact float quotient of the flattened cell loop.  Heat maps threads
 // onto column pairs: pw = fw/2 pairs per row, each thread walks a vertical
 // strip of R rows of one pair, spc = strips per pair column, inv_pw = 1/pw.
+// Heat LDS row pitch = window width + kHeatPad values.
+constexpr int kHeatPad = 1;
+
 struct LevelEntry {
     int x0, y0, fw, fh, hx2, hy2, pw, R, spc;
     float inv_fw, inv_pw;
