@@ -349,13 +349,15 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
 }
 
 // One shape instance (workgroup index blk) of phase a.phase; the body of the
-// phase kernel, also run by the batched persistent kernel.
-template <class S, typename T>
+// phase kernel, also run by the batched persistent kernel.  B > 0 fixes the
+// tile edge at compile time (a.tile must equal it), which turns the window
+// pitch into an immediate in every LDS address; B = 0 takes a.tile.
+template <class S, typename T, int B = 0>
 __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsigned char* smem_raw)
 {
     T* lds = reinterpret_cast<T*>(smem_raw);
     constexpr int NVAR = S::NVAR, R = S::R;
-    const int b = a.tile, h = a.h, N = a.N, L = a.L;
+    const int b = B > 0 ? B : a.tile, h = B > 0 ? B / (2 * R) : a.h, N = a.N, L = a.L;
     // heat pads its LDS rows by one value (fewer bank conflicts between the
     // rows a wave touches at once); Euler keeps the pitch W
     const int W = b + 2 * R, PITCH = W + (NVAR == 1 ? kHeatPad : 0), P = PITCH * W;

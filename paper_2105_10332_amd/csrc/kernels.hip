@@ -28,11 +28,12 @@
 
 namespace swept {
 
-template <class S, typename T>
+// B > 0: heat instantiated for one tile edge (see phase_instance); B = 0: any tile.
+template <class S, typename T, int B>
 __global__ void __launch_bounds__(S::MAXWG) swept_phase_kernel(PhaseArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    phase_instance<S, T>(a, blockIdx.x, smem_raw);
+    phase_instance<S, T, B>(a, blockIdx.x, smem_raw);
 }
 
 // ------------------------------------------------------------ Standard steps
@@ -187,28 +188,41 @@ __global__ void __launch_bounds__(256) cfl_partials(const T* __restrict__ q, siz
 
 // ------------------------------------------------------------------ launchers
 
+// The phase kernel instantiation for a problem: heat at b = 16, 32 or 64
+// gets a fixed-tile copy, everything else the runtime-tile one.
 template <class S, typename T>
-static hipError_t launch_phase_t(const PhaseArgs& a, int wg, size_t lds, hipStream_t st)
+static const void* phase_kernel(int tile)
 {
-    const int t2 = a.tiles * a.tiles;
-    const int nblk = (a.phase & 1) ? 2 * t2 : t2;
-    hipLaunchKernelGGL((swept_phase_kernel<S, T>), dim3(nblk), dim3(wg), lds, st, a);
-    return hipGetLastError();
+    if constexpr (S::NVAR == 1) {
+        if (tile == 64) return (const void*)swept_phase_kernel<S, T, 64>;
+        if (tile == 32) return (const void*)swept_phase_kernel<S, T, 32>;
+        if (tile == 16) return (const void*)swept_phase_kernel<S, T, 16>;
+    }
+    return (const void*)swept_phase_kernel<S, T, 0>;
+}
+
+static const void* phase_kernel(int kind, int dtype, int tile)
+{
+    if (kind == 0) return dtype == 0 ? phase_kernel<HeatS, double>(tile) : phase_kernel<HeatS, float>(tile);
+    return dtype == 0 ? phase_kernel<EulerS, double>(tile) : phase_kernel<EulerS, float>(tile);
 }
 
 hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t lds, hipStream_t st)
 {
-    if (kind == 0) return dtype == 0 ? launch_phase_t<HeatS, double>(a, wg, lds, st)
-                                     : launch_phase_t<HeatS, float>(a, wg, lds, st);
-    return dtype == 0 ? launch_phase_t<EulerS, double>(a, wg, lds, st) : launch_phase_t<EulerS, float>(a, wg, lds, st);
+    const int t2 = a.tiles * a.tiles;
+    const int nblk = (a.phase & 1) ? 2 * t2 : t2;
+    void* args[] = {(void*)&a};
+    return hipLaunchKernel(phase_kernel(kind, dtype, a.tile), dim3(nblk), dim3(wg), args, lds, st);
 }
 
 hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds)
 {
-    const void* f;
-    if (kind == 0) f = dtype == 0 ? (const void*)swept_phase_kernel<HeatS, double> : (const void*)swept_phase_kernel<HeatS, float>;
-    else f = dtype == 0 ? (const void*)swept_phase_kernel<EulerS, double> : (const void*)swept_phase_kernel<EulerS, float>;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipSuccess;
+    for (int tile : {0, 16, 32, 64})
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
+    return e;
 }
 
 hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, double r, hipStream_t st)

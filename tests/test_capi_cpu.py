@@ -105,3 +105,15 @@ def test_cfl_rejects_heat():
     fake = ctypes.c_void_p(0x10000)
     p = heat(64)
     assert L.swept_cfl_dt(ctypes.byref(p), fake, 0.4, fake, 1 << 30, None, ctypes.byref(out)) == CODES["SWEPT_ENOTSUP"]
+
+
+def test_batch_tiles_follow_preferences():
+    """Each problem of a batch takes the largest valid tile not above its kind's preference
+    (the library's own validation decides validity)."""
+    from paper_2105_10332_amd import tune
+
+    specs = [("heat", 1024), ("heat", 160), ("heat", 96), ("euler", 512), ("euler", 288)]
+    got = tune.batch_tiles(specs, "f32", {"heat": 64, "euler": 32})
+    assert got == [64, 32, 48, 32, 32]
+    got = tune.batch_tiles(specs, "f32", {"heat": 16, "euler": 16})
+    assert got == [16, 16, 16, 16, 16]

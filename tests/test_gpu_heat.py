@@ -102,3 +102,44 @@ def test_c2_full_size_closed_form(dtype, tile):
     err = np.abs(sw[js, is_] - exact).max() / np.abs(T0).max()
     print(f"C2 {np.dtype(dtype).name} b={tile}: closed-form error {err:.3e}")
     assert err < (1e-12 if dtype == np.float64 else 2e-5)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_largest_grid_closed_form(dtype):
+    """The largest grid the library accepts (32768^2: 2^30 cells, 8 GiB of FP64 state, byte
+    offsets past 2^32), tile 64, a step count that ends mid-window: Swept equals Standard
+    and sampled cells equal the exact discrete solution of one Fourier mode (P1), which holds
+    at any size."""
+    import torch
+
+    from gpu_helpers import DEV, TDT
+    from paper_2105_10332_amd.solver import HEAT, SweptSolver
+
+    n, M, r, tile = 32768, 37, 0.2, 64
+    p, q, phase = 3, 5, 0.25
+    x = (torch.arange(n, device=DEV, dtype=torch.float64) + 0.5) / n
+    T0 = torch.cos(2 * math.pi * (p * x[None, :] + q * x[:, None]) + phase).to(TDT[dtype])
+    T = T0.clone()
+    dx = 1.0 / n
+    s = SweptSolver(HEAT, T, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile)
+    s.swept_advance(M)
+    r_used = s.info.r
+    s.close()
+    del s
+    Ts = T0.clone()
+    s = SweptSolver(HEAT, Ts, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile)
+    s.standard_advance(M)
+    torch.cuda.synchronize()
+    s.close()
+    del s
+    assert torch.equal(T, Ts)
+    del Ts
+    rng = np.random.default_rng(11)
+    js, is_ = rng.integers(0, n, 400), rng.integers(0, n, 400)
+    got = T[torch.tensor(js, device=DEV), torch.tensor(is_, device=DEV)].double().cpu().numpy()
+    g = 1 - 4 * r_used * (math.sin(math.pi * p / n) ** 2 + math.sin(math.pi * q / n) ** 2)
+    xs = (np.arange(n) + 0.5) / n
+    exact = g ** M * np.cos(2 * math.pi * (p * xs[is_] + q * xs[js]) + phase)
+    err = np.abs(got - exact).max()
+    print(f"{n}^2 {np.dtype(dtype).name}: closed-form error {err:.3e}")
+    assert err < (1e-13 if dtype == np.float64 else 1e-5)
