@@ -306,8 +306,9 @@ __host__ __device__ inline size_t euler_lds_values(int W, int FS) { return (size
 // two paired LDS reads (the next row of both columns; the outer left/right
 // neighbours) and one paired LDS write for two cell-updates (W here is the
 // LDS row pitch).  Cells outside F(l+2) (half-widths hx2, hy2) also go to
-// the level's global buffer.
-template <typename T>
+// the level's global buffer.  WRAP = false when the window does not cross
+// the periodic boundary, so global indices need no wrap.
+template <typename T, bool WRAP>
 __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ gout,
                                            int W, int C, const LevelEntry& e, int hx2, int hy2, int ox, int oy,
                                            int N, T r)
@@ -322,8 +323,8 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
         const int ye = min(ys + e.R, e.y0 + e.fh);
         const bool xk0 = (x - C >= -hx2) && (x - C < hx2);
         const bool xk1 = (x + 1 - C >= -hx2) && (x + 1 - C < hx2);
-        const int gx0 = wrapi(ox + x, N), gx1 = wrapi(ox + x + 1, N);
-        int grow = wrapi(oy + ys, N) * N;
+        const int gx0 = WRAP ? wrapi(ox + x, N) : ox + x, gx1 = WRAP ? wrapi(ox + x + 1, N) : ox + x + 1;
+        int grow = (WRAP ? wrapi(oy + ys, N) : oy + ys) * N;
         int li = ys * W + x;
         T up0 = prev[li - W], up1 = prev[li - W + 1];
         T c0 = prev[li], c1 = prev[li + 1];
@@ -343,7 +344,7 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
             c1 = dn1;
             li += W;
             grow += N;
-            grow = grow >= NN ? grow - NN : grow;
+            if (WRAP) grow = grow >= NN ? grow - NN : grow;
         }
     }
 }
@@ -404,6 +405,8 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         tab = a.tab + (wx > wy ? 2 * h : 3 * h);
         kbase = (wmax - 1) * h;
     }
+    // heat: global indices need the periodic wrap only when the window crosses the boundary
+    const bool wraps = ox < 0 || oy < 0 || ox + W > N || oy + W > N;
     for (int lvl = lo; lvl <= hi; ++lvl) {
         const LevelEntry e = tab[lvl - kbase];
         const bool has2 = lvl + 2 <= hi;
@@ -412,7 +415,10 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         T* cur = lds + (lvl & 1) * BUF;
         T* gout = (lvl & 1) ? g1 : g0;
         if constexpr (NVAR == 1) {
-            heat_level<T>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
+            if (wraps)
+                heat_level<T, true>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
+            else
+                heat_level<T, false>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
         } else {
             T* pbuf = lds + 2 * BUF;
             T* fbuf = pbuf + P;
