@@ -55,7 +55,8 @@ __device__ __forceinline__ void heat_level_pack(const T* __restrict__ prev, T* _
 // (row-major over the same footprint) or, for the cycle's level 0
 // (T_GLOBAL), from the checkpoint in global memory; the two are separate
 // instantiations so that each is read with its own load instructions.
-template <typename T, bool T_GLOBAL>
+// WRAP = false when the window does not cross the periodic boundary.
+template <typename T, bool T_GLOBAL, bool WRAP>
 __device__ __forceinline__ double lambda_level(const T* __restrict__ prev, T* __restrict__ cur,
                                                T* __restrict__ gout, const T* __restrict__ tsrc, int W, int C,
                                                const LevelEntry& e, int hx2, int hy2, int ox, int oy, int N, T r)
@@ -72,7 +73,7 @@ __device__ __forceinline__ double lambda_level(const T* __restrict__ prev, T* __
         const T dyy = (prev[li + W] - two_c) + prev[li - W];
         const T v = (c + r * dxx) + r * dyy;  // the heat update (scheme.h) with its Laplacian kept
         cur[li] = v;
-        const int gx = wrapi(ox + lx, N), gy = wrapi(oy + ly, N);
+        const int gx = WRAP ? wrapi(ox + lx, N) : ox + lx, gy = WRAP ? wrapi(oy + ly, N) : oy + ly;
         const T tv = T_GLOBAL ? tsrc[(size_t)gy * N + gx] : tsrc[i];
         acc += ((double)dxx + (double)dyy) * (double)tv;
         const int dx = lx - C, dy = ly - C;
@@ -116,12 +117,13 @@ __host__ __device__ inline AdjLds adjoint_lds_layout(size_t scalar, int tile, in
 // One reverse phase (k-time phase 0, 1 or 2) of a full cycle of h levels.
 // LDS: one region of two parity windows (forward T, then lambda, then the
 // reduction scratch), the packed forward levels (pk_max values) and their
-// offsets.
-template <typename T>
+// offsets.  B > 0 fixes the tile edge at compile time (a.tile must equal
+// it), so the window pitch is an immediate LDS offset; B = 0 takes a.tile.
+template <typename T, int B>
 __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk_max)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int b = a.tile, h = a.h, N = a.N;
+    const int b = B > 0 ? B : a.tile, h = B > 0 ? B / 2 : a.h, N = a.N;
     const int W = b + 2, P = W * W;
     const size_t NN = (size_t)N * N;
     const int tiles = a.tiles, t2 = tiles * tiles;
@@ -150,6 +152,7 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     const int cx = jx * b + ((fx & 1) ? 0 : b / 2);
     const int cy = jy * b + ((fy & 1) ? 0 : b / 2);
     const int ox = cx - C, oy = cy - C;
+    const bool wraps = ox < 0 || oy < 0 || ox + W > N || oy + W > N;  // window crosses the periodic boundary
     const T r = (T)a.p[0];
 
     // ---- forward recompute of levels j = 1..h-1 of shape (fx, fy) ----
@@ -214,11 +217,18 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
         T* lprev = lpar + ((k - 1) & 1) * P;
         T* lcur = lpar + (k & 1) * P;
         T* gout = (k & 1) ? l1 : l0;
-        if (j >= 1)
-            acc += lambda_level<T, false>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N, r);
-        else
-            acc += lambda_level<T, true>(lprev, lcur, gout, reinterpret_cast<const T*>(a.lvl0), W, C, e, hx2, hy2,
-                                         ox, oy, N, r);
+        const T* tglob = reinterpret_cast<const T*>(a.lvl0);
+        if (wraps) {
+            if (j >= 1)
+                acc += lambda_level<T, false, true>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N, r);
+            else
+                acc += lambda_level<T, true, true>(lprev, lcur, gout, tglob, W, C, e, hx2, hy2, ox, oy, N, r);
+        } else {
+            if (j >= 1)
+                acc += lambda_level<T, false, false>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N, r);
+            else
+                acc += lambda_level<T, true, false>(lprev, lcur, gout, tglob, W, C, e, hx2, hy2, ox, oy, N, r);
+        }
         __syncthreads();
     }
     const double tot = block_sum(acc, red);
@@ -255,21 +265,32 @@ size_t adjoint_lds(int dtype, int tile, int pk_max, int wg)
     return adjoint_lds_layout(dtype == 0 ? 8 : 4, tile, pk_max, wg).total;
 }
 
+// The reverse kernel for a tile: fixed-tile copies at b = 16 and 32, else the runtime-tile one.
+template <typename T>
+static const void* adjoint_kernel(int tile)
+{
+    if (tile == 32) return (const void*)adjoint_phase_kernel<T, 32>;
+    if (tile == 16) return (const void*)adjoint_phase_kernel<T, 16>;
+    return (const void*)adjoint_phase_kernel<T, 0>;
+}
+
 hipError_t set_adjoint_lds_limit(int dtype, size_t lds)
 {
-    const void* f = dtype == 0 ? (const void*)adjoint_phase_kernel<double> : (const void*)adjoint_phase_kernel<float>;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipSuccess;
+    for (int tile : {0, 16, 32})
+        if (e == hipSuccess)
+            e = hipFuncSetAttribute(dtype == 0 ? adjoint_kernel<double>(tile) : adjoint_kernel<float>(tile),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return e;
 }
 
 hipError_t launch_adjoint_phase(int dtype, const PhaseArgs& a, int pk_max, int wg, size_t lds, hipStream_t st)
 {
     const int t2 = a.tiles * a.tiles;
     const int nblk = (a.phase & 1) ? 2 * t2 : t2;
-    if (dtype == 0)
-        hipLaunchKernelGGL(adjoint_phase_kernel<double>, dim3(nblk), dim3(wg), lds, st, a, pk_max);
-    else
-        hipLaunchKernelGGL(adjoint_phase_kernel<float>, dim3(nblk), dim3(wg), lds, st, a, pk_max);
-    return hipGetLastError();
+    void* args[] = {(void*)&a, (void*)&pk_max};
+    return hipLaunchKernel(dtype == 0 ? adjoint_kernel<double>(a.tile) : adjoint_kernel<float>(a.tile), dim3(nblk),
+                           dim3(wg), args, lds, st);
 }
 
 hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const void* Tm, int N, double r,
