@@ -80,7 +80,8 @@ typedef struct {
 } swept_problem;
 
 /* Launch tuning.  tile = block size b of Sec. 3.2 (0: library default);
- * wg = threads per workgroup (0: 256; allowed 64..1024, multiple of 64). */
+ * wg = threads per workgroup (0: 256; a multiple of 64, at most 1024 for heat,
+ * 512 for Euler FP32 and 256 for Euler FP64). */
 typedef struct {
     int32_t tile;
     int32_t wg;
@@ -186,8 +187,9 @@ int swept_destroy(swept_ctx* ctx);
  * taking the shape instances of phase g of every problem (each problem has
  * 1 + 2 ceil(L/h) phases for its own tile), with a grid barrier between
  * global phases.  Every problem's result equals its own swept_advance bit
- * for bit.  Workgroups have 256 threads; tunes[q].tile (or 0 = default)
- * picks each problem's tile, tunes may be NULL. */
+ * for bit.  Workgroups have 512 threads (FP32) or 256 (FP64);
+ * tunes[q].tile (or 0 = default) picks each problem's tile, tunes may be
+ * NULL. */
 typedef struct swept_batch swept_batch;
 
 int swept_batch_workspace_bytes(const swept_problem* probs, const swept_tuning* tunes, int32_t count,

@@ -23,7 +23,7 @@ __device__ __forceinline__ int problem_phases(const PhaseArgs& a, long long n_st
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBatchWG) batch_kernel(const PhaseArgs* __restrict__ probs, int count,
+__global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1)) batch_kernel(const PhaseArgs* __restrict__ probs, int count,
                                                           int nphase_max, long long n_steps)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(kBatchWG) batch_kernel(const PhaseArgs* __rest
 hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu)
 {
     const void* f = dtype == 0 ? (const void*)batch_kernel<double> : (const void*)batch_kernel<float>;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, kBatchWG, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, batch_wg(dtype), lds);
 }
 
 hipError_t set_batch_lds_limit(int dtype, size_t lds)
@@ -77,7 +77,7 @@ hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphas
 {
     void* args[] = {(void*)&d_args, (void*)&count, (void*)&nphase_max, (void*)&n_steps};
     const void* f = dtype == 0 ? (const void*)batch_kernel<double> : (const void*)batch_kernel<float>;
-    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(kBatchWG), args, (unsigned int)lds, st);
+    return hipLaunchCooperativeKernel(f, dim3(grid), dim3(batch_wg(dtype)), args, (unsigned int)lds, st);
 }
 
 }  // namespace swept

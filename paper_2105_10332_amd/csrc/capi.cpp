@@ -114,7 +114,7 @@ int derive(const swept_problem* p, const swept_tuning* t, Derived* d)
         return fail(SWEPT_ESHAPE, "tile %d needs %zu bytes of LDS (max %zu)", tile, d->lds_bytes, kLdsMax);
     int wg = t ? t->wg : 0;
     if (wg == 0) wg = 256;
-    const int wg_max = p->kind == SWEPT_HEAT ? 1024 : 256;
+    const int wg_max = p->kind == SWEPT_HEAT ? 1024 : (p->dtype == SWEPT_F64 ? 256 : 512);
     if (wg < 64 || wg > wg_max || wg % 64 != 0)
         return fail(SWEPT_EINVAL, "wg=%d must be a multiple of 64 in [64,%d]", wg, wg_max);
     d->tile = tile;
@@ -621,7 +621,7 @@ int batch_derive(const swept_problem* probs, const swept_tuning* tunes, int32_t 
     size_t off = 0;
     for (int q = 0; q < count; ++q) {
         if (probs[q].dtype != probs[0].dtype) return fail(SWEPT_EINVAL, "all problems of a batch share one dtype");
-        swept_tuning t{tunes ? tunes[q].tile : 0, swept::kBatchWG};
+        swept_tuning t{tunes ? tunes[q].tile : 0, swept::batch_wg(probs[0].dtype)};
         const int rc = derive(&probs[q], &t, &(*d)[q]);
         if (rc) return rc;
         lay->buf1_off[q] = off;

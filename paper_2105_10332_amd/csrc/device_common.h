@@ -26,8 +26,8 @@ __device__ __forceinline__ int wrapi(int g, int N)
 struct HeatS {
     static constexpr int NVAR = 1, R = 1, TWO_STAGE = 0, MAXWG = 1024;
 };
-struct EulerS {  // register-heavy per-cell update: at most 256 threads so nothing spills
-    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 256;
+struct EulerS {  // register-heavy per-cell update: at most 512 threads (FP32) or 256 (FP64)
+    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 512;
 };
 
 __device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
@@ -347,6 +347,13 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
             if (WRAP) grow = grow >= NN ? grow - NN : grow;
         }
     }
+}
+
+// Largest workgroup of a phase kernel (its launch bound).
+template <class S, typename T>
+constexpr int max_wg()
+{
+    return (S::NVAR == 4 && sizeof(T) == 8) ? 256 : S::MAXWG;
 }
 
 // One shape instance (workgroup index blk) of phase a.phase; the body of the

@@ -30,7 +30,7 @@ namespace swept {
 
 // B > 0: heat instantiated for one tile edge (see phase_instance); B = 0: any tile.
 template <class S, typename T, int B>
-__global__ void __launch_bounds__(S::MAXWG) swept_phase_kernel(PhaseArgs a)
+__global__ void __launch_bounds__((max_wg<S, T>())) swept_phase_kernel(PhaseArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     phase_instance<S, T, B>(a, blockIdx.x, smem_raw);

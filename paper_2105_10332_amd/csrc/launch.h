@@ -74,7 +74,9 @@ hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const voi
 // Batched persistent launch: every problem's phases in one cooperative
 // kernel, global phase g running phase g of every problem that has one.
 constexpr int kBatchMax = 256;
-constexpr int kBatchWG = 256;
+// Threads per batch workgroup: the Euler phase bound of the precision (heat
+// takes any size), 512 in FP32 and 256 in FP64.
+constexpr int batch_wg(int dtype) { return dtype == 0 ? 256 : 512; }
 constexpr size_t kBatchStaticLds = 2048;  // >= sizeof(int) * (kBatchMax + 1), the kernel's static array
 hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu);
 hipError_t set_batch_lds_limit(int dtype, size_t lds);
