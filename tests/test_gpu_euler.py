@@ -75,3 +75,65 @@ def test_c4_full_size_short_run_vs_oracle():
     assert np.array_equal(sw, st)
     ref = oracle.euler_run(Q0, dt, 10 / n, 10 / n, GAMMA, 3)
     assert rel_err(sw, ref) <= 1e-10
+
+
+def _vortex_gpu(n, dtype, length=10.0, eps=5.0, gamma=GAMMA, rows=4096):
+    """The isentropic vortex of problems.shu_vortex built on the GPU in row blocks (input only)."""
+    import math
+
+    x = (torch.arange(n, device=DEV, dtype=torch.float64) + 0.5) * (length / n) - 5.0
+    Q = torch.empty((4, n, n), dtype=dtype, device=DEV)
+    for j0 in range(0, n, rows):
+        Y = x[j0:j0 + rows, None]
+        X = x[None, :]
+        r2 = X * X + Y * Y
+        e = torch.exp(0.5 * (1.0 - r2))
+        u = 1.0 - eps / (2 * math.pi) * Y * e
+        v = 1.0 + eps / (2 * math.pi) * X * e
+        T = 1.0 - (gamma - 1.0) * eps * eps / (8.0 * gamma * math.pi ** 2) * torch.exp(1.0 - r2)
+        rho = T ** (1.0 / (gamma - 1.0))
+        p = rho * T
+        Q[0, j0:j0 + rows] = rho
+        Q[1, j0:j0 + rows] = rho * u
+        Q[2, j0:j0 + rows] = rho * v
+        Q[3, j0:j0 + rows] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return Q
+
+
+def test_largest_grid_sampled_cells():
+    """The largest grid the library accepts (32768^2, FP32: 2^32 values over the four
+    planes), in the FP32 launch configuration (b = 32, 512 threads), three steps: Swept equals
+    Standard bit for bit, and sampled cells in and around the vortex core equal the oracle
+    run on a 40 x 40 periodic patch around each (a cell after three RK2 steps depends only on
+    cells within 12 of it, so the patch's own wrap cannot reach the centre)."""
+    n, M, tile, wg = 32768, 3, 32, 512
+    dx = 10.0 / n
+    dt = 0.4 * dx / 6.5  # below the CFL limit: (|u|+c) + (|v|+c) < 6.5 everywhere on this vortex
+    Q0 = _vortex_gpu(n, torch.float32)
+    Q = Q0.clone()
+    s = SweptSolver(EULER, Q, dt=dt, length=10.0, gamma=GAMMA, tile=tile, wg=wg)
+    s.swept_advance(M)
+    s.close()
+    del s
+    Qs = Q0.clone()
+    s = SweptSolver(EULER, Qs, dt=dt, length=10.0, gamma=GAMMA, tile=tile, wg=wg)
+    s.standard_advance(M)
+    torch.cuda.synchronize()
+    s.close()
+    del s
+    assert torch.equal(Q, Qs)
+    del Qs
+    rng = np.random.default_rng(5)
+    core = rng.integers(int(3.5 / dx), int(6.5 / dx), size=(6, 2))
+    anywhere = rng.integers(0, n, size=(2, 2))
+    scale = Q0.abs().amax(dim=(1, 2)).double().cpu().numpy()
+    worst = 0.0
+    for cy, cx in np.concatenate([core, anywhere]):
+        iy = torch.tensor((np.arange(-20, 20) + cy) % n, device=DEV)
+        ix = torch.tensor((np.arange(-20, 20) + cx) % n, device=DEV)
+        patch = Q0[:, iy][:, :, ix].cpu().numpy()
+        ref = oracle.euler_run(patch, dt, dx, dx, GAMMA, M)[:, 20, 20]
+        got = Q[:, int(cy), int(cx)].cpu().numpy()
+        worst = max(worst, float(np.max(np.abs(got.astype(np.float64) - ref) / scale)))
+    print(f"Euler {n}^2 fp32 sampled cells vs oracle patches: {worst:.3e}")
+    assert worst <= 1e-6
