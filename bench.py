@@ -97,19 +97,20 @@ def cores():
     return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
 
 
-def cpu_heat(dtype_np, n, r, budget_s=12.0):
-    """The oracle as it is on the host cores: one step to size the sample, then a bounded
-    number of Standard steps of the same grid."""
+def cpu_heat(dtype_np, n, r, budget_s=15.0):
+    """The oracle as it is on the host cores: a warm step, a few steps to size the sample,
+    then a bounded number of Standard steps of the same grid (about budget_s seconds)."""
     import numpy as np
 
     import oracle
     from paper_2105_10332_amd import problems
 
     T0 = problems.heat_fourier_modes(n).astype(dtype_np)
-    t = time.perf_counter()
     T1 = oracle.heat_run(T0, r, 1)
-    one = time.perf_counter() - t
-    k = max(1, min(1000, int(budget_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    T1 = oracle.heat_run(T1, r, 4)
+    one = (time.perf_counter() - t) / 4
+    k = max(1, min(5000, int(budget_s / max(one, 1e-6))))
     t = time.perf_counter()
     oracle.heat_run(T1, r, k)
     el = time.perf_counter() - t
@@ -118,17 +119,18 @@ def cpu_heat(dtype_np, n, r, budget_s=12.0):
                       f"(OpenMP over rows), {el:.1f} s"}
 
 
-def cpu_euler(dtype_np, n, dt, budget_s=12.0):
+def cpu_euler(dtype_np, n, dt, budget_s=15.0):
     import numpy as np
 
     import oracle
     from paper_2105_10332_amd import problems
 
     Q0 = problems.shu_vortex(n).astype(dtype_np)
-    t = time.perf_counter()
     Q1 = oracle.euler_run(Q0, dt, 10 / n, 10 / n, 1.4, 1)
-    one = time.perf_counter() - t
-    k = max(1, min(500, int(budget_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    Q1 = oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, 2)
+    one = (time.perf_counter() - t) / 2
+    k = max(1, min(1000, int(budget_s / max(one, 1e-6))))
     t = time.perf_counter()
     oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, k)
     el = time.perf_counter() - t

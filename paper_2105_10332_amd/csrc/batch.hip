@@ -23,8 +23,8 @@ __device__ __forceinline__ int problem_phases(const PhaseArgs& a, long long n_st
 }
 
 template <typename T>
-__global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1)) batch_kernel(const PhaseArgs* __restrict__ probs, int count,
-                                                          int nphase_max, long long n_steps)
+__global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
+    batch_kernel(const PhaseArgs* __restrict__ probs, int count, int nphase_max, long long n_steps)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int pre[kBatchMax + 1];
