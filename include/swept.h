@@ -185,9 +185,11 @@ int swept_destroy(swept_ctx* ctx);
  * advanced together by a single cooperative kernel: the grid holds what the
  * GPU keeps resident, and every workgroup walks global phases g = 0, 1, ...,
  * taking the shape instances of phase g of every problem (each problem has
- * 1 + 2 ceil(L/h) phases for its own tile), with a grid barrier between
- * global phases.  Every problem's result equals its own swept_advance bit
- * for bit.  Workgroups have 512 threads (FP32) or 256 (FP64);
+ * 1 + 2 ceil(L/h) phases for its own tile) from a per-phase atomic counter,
+ * with a grid barrier between global phases.  Every problem's result equals
+ * its own swept_advance bit for bit.  The workspace holds each problem's
+ * second level-parity buffer and level table, the launch arguments and the
+ * two phase counters; calls that overlap on one workspace race.  Workgroups have 512 threads (FP32) or 256 (FP64);
  * tunes[q].tile (or 0 = default) picks each problem's tile, tunes may be
  * NULL. */
 typedef struct swept_batch swept_batch;

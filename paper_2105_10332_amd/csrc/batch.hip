@@ -1,12 +1,17 @@
 // batch.hip -- many swept problems of uneven size in one persistent launch.
 //
 // The grid is sized to what the GPU holds resident (cooperative launch), and
-// every workgroup walks global phases g = 0, 1, ...: in phase g it takes,
-// grid-stride, the shape instances of phase g of every problem that has one
-// (each problem has 1 + 2 ceil(L/h) phases for its own tile and level count),
-// runs each exactly like the single-problem phase kernel, and then waits at
-// a grid barrier.  Problems are independent, so one barrier per global phase
-// is the only synchronisation; heat and Euler instances share the launch.
+// every workgroup walks global phases g = 0, 1, ...: in phase g it takes the
+// shape instances of phase g of every problem that has one (each problem has
+// 1 + 2 ceil(L/h) phases for its own tile and level count) -- grid-stride in
+// phase 0, then one at a time from a per-phase atomic counter, so faster
+// workgroups take more of the uneven instances -- runs each exactly like the
+// single-problem phase kernel, and then waits at a grid barrier.  Problems are
+// independent, so one barrier per global phase is the only synchronisation;
+// heat and Euler instances share the launch.  The two counters alternate
+// between phases: workgroup 0 clears the next phase's counter while the
+// current phase runs (nobody touches it then), and the grid barrier
+// publishes the clear.
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
@@ -24,10 +29,11 @@ __device__ __forceinline__ int problem_phases(const PhaseArgs& a, long long n_st
 
 template <typename T>
 __global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
-    batch_kernel(const PhaseArgs* __restrict__ probs, int count, int nphase_max, long long n_steps)
+    batch_kernel(const PhaseArgs* __restrict__ probs, int count, int nphase_max, long long n_steps, int* ctr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ int pre[kBatchMax + 1];
+    __shared__ int s_it;
     cg::grid_group grid = cg::this_grid();
     for (int gp = 0; gp < nphase_max; ++gp) {
         if (threadIdx.x == 0) {  // items of this global phase, problem by problem
@@ -39,10 +45,20 @@ __global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
                 if (gp < problem_phases(a, n_steps)) tot += (gp & 1) ? 2 * t2 : t2;
             }
             pre[count] = tot;
+            if (blockIdx.x == 0) ctr[(gp + 1) & 1] = 0;  // the next phase's counter is idle during this one
         }
         __syncthreads();
         const int total = pre[count];
-        for (int it = blockIdx.x; it < total; it += gridDim.x) {
+        for (int k = 0;; ++k) {
+            int it;
+            if (gp == 0) {
+                it = blockIdx.x + k * gridDim.x;
+            } else {
+                if (threadIdx.x == 0) s_it = atomicAdd(&ctr[gp & 1], 1);
+                __syncthreads();
+                it = s_it;
+            }
+            if (it >= total) break;
             int lo = 0, hi = count;  // largest q with pre[q] <= it
             while (hi - lo > 1) {
                 const int mid = (lo + hi) >> 1;
@@ -73,9 +89,9 @@ hipError_t set_batch_lds_limit(int dtype, size_t lds)
 }
 
 hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphase_max, long long n_steps, int grid,
-                        size_t lds, hipStream_t st)
+                        size_t lds, hipStream_t st, int* ctr)
 {
-    void* args[] = {(void*)&d_args, (void*)&count, (void*)&nphase_max, (void*)&n_steps};
+    void* args[] = {(void*)&d_args, (void*)&count, (void*)&nphase_max, (void*)&n_steps, (void*)&ctr};
     const void* f = dtype == 0 ? (const void*)batch_kernel<double> : (const void*)batch_kernel<float>;
     return hipLaunchCooperativeKernel(f, dim3(grid), dim3(batch_wg(dtype)), args, (unsigned int)lds, st);
 }

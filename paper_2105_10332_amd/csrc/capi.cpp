@@ -598,6 +598,7 @@ struct swept_batch {
     std::vector<Derived> d;
     std::vector<void*> states, buf1s;
     swept::PhaseArgs* dev_args = nullptr;
+    int* ctr = nullptr;
     size_t lds = 0;
     int grid = 0;
 };
@@ -606,7 +607,7 @@ namespace {
 
 struct BatchLayout {
     std::vector<size_t> buf1_off, tab_off;
-    size_t args_off, total;
+    size_t args_off, ctr_off, total;
 };
 
 int batch_derive(const swept_problem* probs, const swept_tuning* tunes, int32_t count, std::vector<Derived>* d,
@@ -630,7 +631,8 @@ int batch_derive(const swept_problem* probs, const swept_tuning* tunes, int32_t 
         off += align_up(table_bytes((*d)[q]));
     }
     lay->args_off = off;
-    lay->total = off + align_up(sizeof(swept::PhaseArgs) * count);
+    lay->ctr_off = off + align_up(sizeof(swept::PhaseArgs) * count);
+    lay->total = lay->ctr_off + align_up(2 * sizeof(int));
     return SWEPT_OK;
 }
 
@@ -702,6 +704,7 @@ int swept_batch_init(swept_batch** ctx, const swept_problem* probs, const swept_
         }
     }
     b->dev_args = reinterpret_cast<swept::PhaseArgs*>(w + lay.args_off);
+    b->ctr = reinterpret_cast<int*>(w + lay.ctr_off);
     // the batch kernel also has a small static LDS array (its per-phase item prefix)
     const size_t dyn_max = kLdsMax - swept::kBatchStaticLds;
     if (b->lds > dyn_max) {
@@ -744,7 +747,7 @@ int swept_batch_advance(swept_batch* b, int64_t n_steps)
         nph = std::max(nph, (int)(2 * ((L + b->d[q].h - 1) / b->d[q].h) + 1));
     }
     hipError_t e = swept::launch_batch(b->dtype, b->dev_args, b->count, nph, (long long)n_steps, b->grid, b->lds,
-                                       b->stream);
+                                       b->stream, b->ctr);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     for (int q = 0; q < b->count; ++q) {
         if ((n_steps * b->d[q].lps) & 1) {
