@@ -38,7 +38,7 @@ METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB
 # WRITE_SIZE x 1.0: the factors a plain copy of known size reads), keyed by workload and launch
 # shape, valid only for the kernel sources whose hash is recorded with it (null otherwise).
 MEASURED_TRAFFIC = {
-    ("heat", "f64", 4096, 64, 512, 1000): (629.5e6, "91e51562b44c65cb"),
+    ("heat", "f64", 4096, 64, 512, 1000): (629.6e6, "2a6ae5ce1977172a"),
 }
 KERNEL_SOURCES = ("scheme.h", "device_common.h", "kernels.hip", "launch.h")
 
@@ -97,7 +97,7 @@ def cores():
     return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
 
 
-def cpu_heat(dtype_np, n, r, budget_s=15.0):
+def cpu_heat(dtype_np, n, r, budget_s=25.0):
     """The oracle as it is on the host cores: a warm step, a few steps to size the sample,
     then a bounded number of Standard steps of the same grid (about budget_s seconds)."""
     import numpy as np
