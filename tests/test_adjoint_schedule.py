@@ -11,7 +11,8 @@ from paper_2105_10332_amd import problems
 from adjoint_sim import AdjointSim
 
 
-@pytest.mark.parametrize("N,b,M", [(16, 8, 8), (16, 8, 12), (24, 8, 16), (32, 16, 24), (24, 12, 18), (20, 10, 15)])
+@pytest.mark.parametrize("N,b,M", [(16, 8, 8), (16, 8, 12), (24, 8, 16), (32, 16, 24), (24, 12, 18), (20, 10, 15),
+                                   (8, 4, 8)])
 def test_swept_adjoint_equals_oracle(N, b, M):
     T0 = problems.heat_fourier_modes(N, seed=problems.SEED_ADJ_T0)
     Ts = problems.heat_fourier_modes(N, seed=problems.SEED_ADJ_TARGET)

@@ -34,7 +34,7 @@ def gpu_adjoint(T0, g, r, steps, tile, dtype):
 
 
 @pytest.mark.parametrize("N,tile,steps", [(32, 8, 8), (32, 8, 13), (48, 16, 24), (64, 16, 40), (64, 32, 48),
-                                          (64, 32, 35), (36, 12, 18), (40, 10, 17)])
+                                          (64, 32, 35), (36, 12, 18), (40, 10, 17), (8, 4, 8), (12, 4, 7)])
 def test_adjoint_matches_oracle_fp64(N, tile, steps):
     T0 = problems.heat_fourier_modes(N, seed=problems.SEED_ADJ_T0)
     Ts = problems.heat_fourier_modes(N, seed=problems.SEED_ADJ_TARGET)

@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("tile,N", [(8, 16), (8, 40), (16, 32), (16, 48), (32, 64), (32, 96), (64, 128), (6, 18),
-                                    (12, 36)])
+                                    (12, 36), (4, 8), (4, 12)])
 def test_swept_equals_standard_and_oracle(dtype, tile, N):
     h = tile // 2
     T0 = problems.heat_sine_noise(N, seed=tile + N).astype(dtype)

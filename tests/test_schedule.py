@@ -15,7 +15,7 @@ from swept_sim import Geom, SweptSim, check_partition
 
 HEAT_CASES = [  # (N, b, L): N in {2b, 3b, 4b}; L a multiple of h and not; odd h (b = 6, 10)
     (16, 8, 1), (16, 8, 4), (16, 8, 9), (24, 8, 16), (32, 8, 13), (32, 16, 21), (48, 16, 8),
-    (24, 12, 13), (18, 6, 10), (30, 10, 11), (64, 32, 20),
+    (24, 12, 13), (18, 6, 10), (30, 10, 11), (64, 32, 20), (8, 4, 5), (12, 4, 8),  # b = 4: the smallest window, h = 2
 ]
 EULER_CASES = [  # stage-levels L (even = whole RK2 steps); h = b/4
     (16, 8, 2), (16, 8, 10), (32, 16, 12), (32, 16, 18), (24, 12, 14), (48, 16, 20), (40, 20, 16),
