@@ -117,3 +117,15 @@ def test_batch_tiles_follow_preferences():
     assert got == [64, 32, 48, 32, 32]
     got = tune.batch_tiles(specs, "f32", {"heat": 16, "euler": 16})
     assert got == [16, 16, 16, 16, 16]
+
+
+def test_batch_count_and_dtype_validation():
+    """A batch takes 1..256 problems of one dtype; anything else is rejected before any HIP call."""
+    L = _lib.lib()
+    out = ctypes.c_size_t(0)
+    probs = (Problem * 257)(*[heat(32) for _ in range(257)])
+    assert L.swept_batch_workspace_bytes(probs, None, 256, ctypes.byref(out)) == 0 and out.value > 0
+    assert L.swept_batch_workspace_bytes(probs, None, 257, ctypes.byref(out)) == CODES["SWEPT_EINVAL"]
+    assert L.swept_batch_workspace_bytes(probs, None, 0, ctypes.byref(out)) == CODES["SWEPT_EINVAL"]
+    mixed = (Problem * 2)(heat(32, dtype=0), heat(32, dtype=1))
+    assert L.swept_batch_workspace_bytes(mixed, None, 2, ctypes.byref(out)) == CODES["SWEPT_EINVAL"]

@@ -62,3 +62,23 @@ def test_batch_vs_oracle_and_twice():
         else:
             ref = oracle.euler_run(init[q], dt, 10 / n, 10 / n, 1.4, 23)
         assert rel_err(x.cpu().numpy(), ref) <= 1e-10
+
+
+def test_batch_largest_count():
+    """The largest batch the library takes (256 problems, small and mixed, FP32), 9 steps:
+    every problem equals its own swept advance."""
+    kinds = [(HEAT, 16, 8, 0.2), (HEAT, 24, 4, 0.1), (EULER, 16, 8, 3.0), (HEAT, 32, 16, 0.24), (EULER, 24, 12, 1.5)]
+    spec = [kinds[q % len(kinds)] for q in range(256)]
+    items = _items(torch.float32, spec)
+    refs = []
+    for kind, x, dt, length, alpha, gamma, tile in items:
+        y = x.clone()
+        s = SweptSolver(kind, y, dt=dt, length=length, alpha=alpha, gamma=gamma, tile=tile)
+        s.swept_advance(9)
+        s.close()
+        refs.append(y)
+    b = SweptBatch(items)
+    b.swept_batch_advance(9)
+    torch.cuda.synchronize()
+    for q, ((kind, x, *_), y) in enumerate(zip(items, refs)):
+        assert torch.equal(x, y), (q, spec[q])
