@@ -11,9 +11,10 @@
 
 namespace swept {
 
-// Exact quotient i / d for 0 <= i < 2^13 and 1 <= d <= 160 from a float
-// reciprocal: the rounding error of (i + 0.5) * inv stays far below the
-// 0.5/d distance of (i + 0.5)/d to an integer.
+// Exact quotient i / d from a float reciprocal inv = 1.0f/d: the rounding
+// error of (i + 0.5) * inv stays below the 0.5/d distance of (i + 0.5)/d to
+// an integer.  Checked exhaustively for 0 <= i < 2^21, 1 <= d <= 160 (the
+// kernels use i < 2^15 and d < 150: window cells, thread indices, widths).
 __device__ __forceinline__ int qdiv(int i, float inv) { return (int)(((float)i + 0.5f) * inv); }
 
 __device__ __forceinline__ int wrapi(int g, int N)
