@@ -136,6 +136,9 @@ __global__ void __launch_bounds__(256) plane_sum_partials(const T* __restrict__ 
     if (threadIdx.x == 0) partials[plane * gridDim.x + blockIdx.x] = red[0];
 }
 
+// Maximum that propagates NaN (a non-finite rate must not be skipped by the max).
+__device__ __forceinline__ double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
+
 __global__ void __launch_bounds__(256) combine_partials(const double* __restrict__ partials, int nparts, int op_max,
                                                         double* __restrict__ out)
 {
@@ -144,14 +147,14 @@ __global__ void __launch_bounds__(256) combine_partials(const double* __restrict
     double s = op_max ? -INFINITY : 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
         const double v = partials[plane * nparts + i];
-        s = op_max ? (v > s ? v : s) : s + v;
+        s = op_max ? nan_max(v, s) : s + v;
     }
     red[threadIdx.x] = s;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
         if ((int)threadIdx.x < w) {
             const double o = red[threadIdx.x + w];
-            red[threadIdx.x] = op_max ? (o > red[threadIdx.x] ? o : red[threadIdx.x]) : red[threadIdx.x] + o;
+            red[threadIdx.x] = op_max ? nan_max(o, red[threadIdx.x]) : red[threadIdx.x] + o;
         }
         __syncthreads();
     }
@@ -174,13 +177,12 @@ __global__ void __launch_bounds__(256) cfl_partials(const T* __restrict__ q, siz
         const double p = (gamma - 1.0) * (E - 0.5 * (mu * u + mv * v));
         const double c = sqrt(gamma * p / rho);
         const double s = (fabs(u) + c) / dx + (fabs(v) + c) / dy;
-        m = s > m ? s : m;
+        m = nan_max(s, m);
     }
     red[threadIdx.x] = m;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = red[threadIdx.x + w] > red[threadIdx.x] ? red[threadIdx.x + w]
-                                                                                               : red[threadIdx.x];
+        if ((int)threadIdx.x < w) red[threadIdx.x] = nan_max(red[threadIdx.x + w], red[threadIdx.x]);
         __syncthreads();
     }
     if (threadIdx.x == 0) partials[blockIdx.x] = red[0];

@@ -137,3 +137,15 @@ def test_largest_grid_sampled_cells():
         worst = max(worst, float(np.max(np.abs(got.astype(np.float64) - ref) / scale)))
     print(f"Euler {n}^2 fp32 sampled cells vs oracle patches: {worst:.3e}")
     assert worst <= 1e-6
+
+
+def test_cfl_rejects_nonphysical_state():
+    """A state with negative pressure has no sound speed: swept_cfl_dt reports
+    SWEPT_ENONFINITE rather than a time step."""
+    from paper_2105_10332_amd._lib import SweptError
+
+    Q = torch.tensor(problems.shu_vortex(32), device=DEV)
+    Q[3, 10, 10] = 0.0  # E = 0 with nonzero momentum: p < 0
+    with pytest.raises(SweptError) as ei:
+        swept_cfl_dt(Q, 10.0, 0.4)
+    assert ei.value.name == "SWEPT_ENONFINITE"

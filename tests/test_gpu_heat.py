@@ -143,3 +143,23 @@ def test_largest_grid_closed_form(dtype):
     err = np.abs(got - exact).max()
     print(f"{n}^2 {np.dtype(dtype).name}: closed-form error {err:.3e}")
     assert err < (1e-13 if dtype == np.float64 else 1e-5)
+
+
+def test_nonfinite_state_is_reported():
+    """swept_conserved reports a non-finite plane sum as SWEPT_ENONFINITE (after a swept
+    advance has spread a NaN), instead of returning it as a number."""
+    import torch
+
+    from gpu_helpers import DEV
+    from paper_2105_10332_amd._lib import SweptError
+    from paper_2105_10332_amd.solver import HEAT, SweptSolver
+
+    T = torch.tensor(problems.heat_sine_noise(32), device=DEV)
+    s = SweptSolver(HEAT, T, dt=0.2 / 32 / 32, length=1.0, alpha=1.0, tile=8)
+    assert math.isfinite(s.swept_conserved()[0])
+    T[5, 7] = float("nan")
+    s.swept_advance(3)
+    with pytest.raises(SweptError) as ei:
+        s.swept_conserved()
+    assert ei.value.name == "SWEPT_ENONFINITE"
+    s.close()
