@@ -94,7 +94,7 @@ def best_tile(kind: str, dtype: str, n: int) -> int:
     return best(kind, dtype, n)[0]
 
 
-def tune(kind: str, dtype: str, n: int, steps: int = 0, reps: int = 2, save: bool = True, verbose: bool = False):
+def tune(kind: str, dtype: str, n: int, steps: int = 0, reps: int = 3, save: bool = True, verbose: bool = False):
     """Time every candidate on the GPU (swept advance of `steps` steps, default a few
     windows of the deepest tile) and cache the fastest."""
     import torch
@@ -107,11 +107,11 @@ def tune(kind: str, dtype: str, n: int, steps: int = 0, reps: int = 2, save: boo
     if kind == "heat":
         x0 = torch.tensor(problems.heat_fourier_modes(n), dtype=tdt, device=dev)
         mk = lambda b, wg, x: SweptSolver(HEAT, x, dt=0.2 / n / n, length=1.0, alpha=1.0, tile=b, wg=wg)
-        steps = steps or 128
+        steps = steps or 512
     else:
         x0 = torch.tensor(problems.shu_vortex(n), dtype=tdt, device=dev)
         mk = lambda b, wg, x: SweptSolver(EULER, x, dt=0.4 * (10.0 / n) / 6.0, length=10.0, tile=b, wg=wg)
-        steps = steps or 32
+        steps = steps or 64
     results = []
     for b, wg in candidates(kind, dtype, n):
         x = x0.clone()
