@@ -160,8 +160,9 @@ int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, voi
  * inside its reverse Octahedra, Bridges and Pyramids in LDS.  Heat only;
  * the tile must satisfy the LDS limit of the reverse shapes (tile <= 32). */
 
-/* Bytes of tape for an n_steps adjoint: ceil(n_steps/h) checkpoints, six
- * state-sized scratch buffers, (n_steps mod h) stored levels and the
+/* Bytes of tape for an n_steps adjoint: ceil(n_steps/h) checkpoints, four
+ * state-sized scratch buffers, two double planes for lambda (carried in
+ * double for both state precisions), (n_steps mod h) stored levels and the
  * partial sums.  SWEPT_ENOTSUP for Euler, SWEPT_ESHAPE if the tile is too
  * large for the adjoint. */
 int swept_tape_bytes(const swept_ctx* ctx, int64_t n_steps, size_t* bytes);

@@ -56,10 +56,12 @@ __device__ __forceinline__ void heat_level_pack(const T* __restrict__ prev, T* _
 // (T_GLOBAL), from the checkpoint in global memory; the two are separate
 // instantiations so that each is read with its own load instructions.
 // WRAP = false when the window does not cross the periodic boundary.
-template <typename T, bool T_GLOBAL, bool WRAP>
-__device__ __forceinline__ double lambda_level(const T* __restrict__ prev, T* __restrict__ cur,
-                                               T* __restrict__ gout, const T* __restrict__ tsrc, int W, int C,
-                                               const LevelEntry& e, int hx2, int hy2, int ox, int oy, int N, T r)
+// Lambda has its own type L (double for both state precisions); T is the
+// forward state's type.
+template <typename L, typename T, bool T_GLOBAL, bool WRAP>
+__device__ __forceinline__ double lambda_level(const L* __restrict__ prev, L* __restrict__ cur,
+                                               L* __restrict__ gout, const T* __restrict__ tsrc, int W, int C,
+                                               const LevelEntry& e, int hx2, int hy2, int ox, int oy, int N, L r)
 {
     const int fw = e.fw, cells = fw * e.fh;
     double acc = 0.0;
@@ -67,11 +69,11 @@ __device__ __forceinline__ double lambda_level(const T* __restrict__ prev, T* __
         const int q = qdiv(i, e.inv_fw);
         const int lx = e.x0 + (i - q * fw), ly = e.y0 + q;
         const int li = ly * W + lx;
-        const T c = prev[li];
-        const T two_c = c + c;
-        const T dxx = (prev[li + 1] - two_c) + prev[li - 1];
-        const T dyy = (prev[li + W] - two_c) + prev[li - W];
-        const T v = (c + r * dxx) + r * dyy;  // the heat update (scheme.h) with its Laplacian kept
+        const L c = prev[li];
+        const L two_c = c + c;
+        const L dxx = (prev[li + 1] - two_c) + prev[li - 1];
+        const L dyy = (prev[li + W] - two_c) + prev[li - W];
+        const L v = (c + r * dxx) + r * dyy;  // the heat update (scheme.h) with its Laplacian kept
         cur[li] = v;
         const int gx = WRAP ? wrapi(ox + lx, N) : ox + lx, gy = WRAP ? wrapi(oy + ly, N) : oy + ly;
         const T tv = T_GLOBAL ? tsrc[(size_t)gy * N + gx] : tsrc[i];
@@ -102,11 +104,11 @@ __device__ __forceinline__ double block_sum(double v, double* red)
 struct AdjLds {
     size_t pk, offs, total;
 };
-__host__ __device__ inline AdjLds adjoint_lds_layout(size_t scalar, int tile, int pk_max, int wg)
+__host__ __device__ inline AdjLds adjoint_lds_layout(size_t scalar, size_t lscalar, int tile, int pk_max, int wg)
 {
     const size_t W = tile + 2;
     const int h = tile / 2;
-    const size_t win = scalar * 2 * W * W, red = sizeof(double) * wg;
+    const size_t win = (scalar > lscalar ? scalar : lscalar) * 2 * W * W, red = sizeof(double) * wg;
     AdjLds l;
     l.pk = ((win > red ? win : red) + 15) / 16 * 16;
     l.offs = (l.pk + scalar * pk_max + 15) / 16 * 16;
@@ -122,14 +124,15 @@ __host__ __device__ inline AdjLds adjoint_lds_layout(size_t scalar, int tile, in
 template <typename T, int B>
 __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk_max)
 {
+    using L = double;  // lambda
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int b = B > 0 ? B : a.tile, h = B > 0 ? B / 2 : a.h, N = a.N;
     const int W = b + 2, P = W * W;
     const size_t NN = (size_t)N * N;
     const int tiles = a.tiles, t2 = tiles * tiles;
-    const AdjLds lay = adjoint_lds_layout(sizeof(T), b, pk_max, blockDim.x);
+    const AdjLds lay = adjoint_lds_layout(sizeof(T), sizeof(L), b, pk_max, blockDim.x);
     T* tpar = reinterpret_cast<T*>(smem_raw);
-    T* lpar = tpar;  // the forward windows are dead once every level is packed
+    L* lpar = reinterpret_cast<L*>(smem_raw);  // the forward windows are dead once every level is packed
     T* pk = reinterpret_cast<T*>(smem_raw + lay.pk);
     int* offs = reinterpret_cast<int*>(smem_raw + lay.offs);  // packed offset of each forward level
     double* red = reinterpret_cast<double*>(smem_raw);  // after the last lambda level
@@ -154,6 +157,7 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     const int ox = cx - C, oy = cy - C;
     const bool wraps = ox < 0 || oy < 0 || ox + W > N || oy + W > N;  // window crosses the periodic boundary
     const T r = (T)a.p[0];
+    const L rl = (L)r;  // lambda runs the transpose of exactly the forward's (T-rounded) operator
 
     // ---- forward recompute of levels j = 1..h-1 of shape (fx, fy) ----
     const int flo = 1, fhi = h - 1;
@@ -192,9 +196,9 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     const int klo = max(1, (kmax - 1) * h + 1);
     const int khi = min(h, (kmin + 1) * h - 1);
     {
-        const RingSrc<T> src{reinterpret_cast<const T*>(a.lam0), reinterpret_cast<const T*>(a.lam1),
-                             reinterpret_cast<const T*>(a.lam0), nullptr, nullptr, false};
-        preload_rings<HeatS, T>(lpar, P, src, W, P, W, N, NN, ox, oy, kx, ky, klo, khi, h, C);
+        const RingSrc<L> src{reinterpret_cast<const L*>(a.lam0), reinterpret_cast<const L*>(a.lam1),
+                             reinterpret_cast<const L*>(a.lam0), nullptr, nullptr, false};
+        preload_rings<HeatS, L>(lpar, P, src, W, P, W, N, NN, ox, oy, kx, ky, klo, khi, h, C);
     }
     const LevelEntry* ktab;
     int kkbase;
@@ -206,28 +210,29 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
         kkbase = (kmax - 1) * h;
     }
     __syncthreads();
-    T* l0 = reinterpret_cast<T*>(a.lam0);
-    T* l1 = reinterpret_cast<T*>(a.lam1);
+    L* l0 = reinterpret_cast<L*>(a.lam0);
+    L* l1 = reinterpret_cast<L*>(a.lam1);
     double acc = 0.0;
     for (int k = klo; k <= khi; ++k) {
         const LevelEntry e = ktab[k - kkbase];
         const bool has2 = k + 2 <= khi;
         const int hx2 = has2 ? e.hx2 : 0, hy2 = has2 ? e.hy2 : 0;
         const int j = h - k;
-        T* lprev = lpar + ((k - 1) & 1) * P;
-        T* lcur = lpar + (k & 1) * P;
-        T* gout = (k & 1) ? l1 : l0;
+        L* lprev = lpar + ((k - 1) & 1) * P;
+        L* lcur = lpar + (k & 1) * P;
+        L* gout = (k & 1) ? l1 : l0;
         const T* tglob = reinterpret_cast<const T*>(a.lvl0);
         if (wraps) {
             if (j >= 1)
-                acc += lambda_level<T, false, true>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N, r);
+                acc += lambda_level<L, T, false, true>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N, rl);
             else
-                acc += lambda_level<T, true, true>(lprev, lcur, gout, tglob, W, C, e, hx2, hy2, ox, oy, N, r);
+                acc += lambda_level<L, T, true, true>(lprev, lcur, gout, tglob, W, C, e, hx2, hy2, ox, oy, N, rl);
         } else {
             if (j >= 1)
-                acc += lambda_level<T, false, false>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N, r);
+                acc += lambda_level<L, T, false, false>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N,
+                                                        rl);
             else
-                acc += lambda_level<T, true, false>(lprev, lcur, gout, tglob, W, C, e, hx2, hy2, ox, oy, N, r);
+                acc += lambda_level<L, T, true, false>(lprev, lcur, gout, tglob, W, C, e, hx2, hy2, ox, oy, N, rl);
         }
         __syncthreads();
     }
@@ -236,11 +241,12 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
 }
 
 // Remainder steps (a run whose length is not a multiple of h): one adjoint
-// step per launch over the whole grid, lambda_out = A lambda_in, with the
-// pairing against the stored forward level T^m; per-block partial sums.
+// step per launch over the whole grid, lambda_out = A lambda_in (lambda in
+// double), with the pairing against the stored forward level T^m; per-block
+// partial sums.
 template <typename T>
-__global__ void __launch_bounds__(256) adjoint_step_kernel(const T* __restrict__ lin, T* __restrict__ lout,
-                                                           const T* __restrict__ Tm, int N, T r,
+__global__ void __launch_bounds__(256) adjoint_step_kernel(const double* __restrict__ lin, double* __restrict__ lout,
+                                                           const T* __restrict__ Tm, int N, double r,
                                                            double* __restrict__ partials)
 {
     __shared__ double red[256];
@@ -249,12 +255,12 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* __restrict__
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < NN; i += (size_t)gridDim.x * blockDim.x) {
         const int y = (int)(i / N), x = (int)(i - (size_t)y * N);
         const size_t row = (size_t)y * N;
-        const T c = lin[i];
-        const T two_c = c + c;
-        const T dxx = (lin[row + wrapi(x + 1, N)] - two_c) + lin[row + wrapi(x - 1, N)];
-        const T dyy = (lin[(size_t)wrapi(y + 1, N) * N + x] - two_c) + lin[(size_t)wrapi(y - 1, N) * N + x];
+        const double c = lin[i];
+        const double two_c = c + c;
+        const double dxx = (lin[row + wrapi(x + 1, N)] - two_c) + lin[row + wrapi(x - 1, N)];
+        const double dyy = (lin[(size_t)wrapi(y + 1, N) * N + x] - two_c) + lin[(size_t)wrapi(y - 1, N) * N + x];
         lout[i] = (c + r * dxx) + r * dyy;
-        acc += ((double)dxx + (double)dyy) * (double)Tm[i];
+        acc += (dxx + dyy) * (double)Tm[i];
     }
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -262,7 +268,36 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const T* __restrict__
 
 size_t adjoint_lds(int dtype, int tile, int pk_max, int wg)
 {
-    return adjoint_lds_layout(dtype == 0 ? 8 : 4, tile, pk_max, wg).total;
+    return adjoint_lds_layout(dtype == 0 ? 8 : 4, sizeof(double), tile, pk_max, wg).total;
+}
+
+// Lambda is kept in double: the seed dJ/dT^M is widened into it and dJ/dT^0
+// narrowed out of it in the state's type.
+template <typename T>
+__global__ void widen_kernel(const T* __restrict__ x, double* __restrict__ y, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (double)x[i];
+}
+
+template <typename T>
+__global__ void narrow_kernel(const double* __restrict__ x, T* __restrict__ y, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        y[i] = (T)x[i];
+}
+
+hipError_t launch_lambda_convert(int dtype, const void* src, void* dst, size_t n, bool widen, hipStream_t st)
+{
+    const dim3 grd(1024), blk(256);
+    if (widen) {
+        if (dtype == 0) hipLaunchKernelGGL(widen_kernel<double>, grd, blk, 0, st, (const double*)src, (double*)dst, n);
+        else hipLaunchKernelGGL(widen_kernel<float>, grd, blk, 0, st, (const float*)src, (double*)dst, n);
+    } else {
+        if (dtype == 0) hipLaunchKernelGGL(narrow_kernel<double>, grd, blk, 0, st, (const double*)src, (double*)dst, n);
+        else hipLaunchKernelGGL(narrow_kernel<float>, grd, blk, 0, st, (const double*)src, (float*)dst, n);
+    }
+    return hipGetLastError();
 }
 
 // The reverse kernel for a tile: fixed-tile copies at b = 16 and 32, else the runtime-tile one.
@@ -299,9 +334,9 @@ hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const voi
     if (dtype == 0)
         hipLaunchKernelGGL(adjoint_step_kernel<double>, dim3(nblocks), dim3(256), 0, st, (const double*)lin,
                            (double*)lout, (const double*)Tm, N, r, partials);
-    else
-        hipLaunchKernelGGL(adjoint_step_kernel<float>, dim3(nblocks), dim3(256), 0, st, (const float*)lin,
-                           (float*)lout, (const float*)Tm, N, (float)r, partials);
+    else  // the forward ran with r rounded to float; lambda runs the transpose of that operator
+        hipLaunchKernelGGL(adjoint_step_kernel<float>, dim3(nblocks), dim3(256), 0, st, (const double*)lin,
+                           (double*)lout, (const float*)Tm, N, (double)(float)r, partials);
     return hipGetLastError();
 }
 

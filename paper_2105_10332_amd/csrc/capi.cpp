@@ -153,10 +153,10 @@ int tape_plan(const Derived& d, int nx, int64_t n_steps, TapePlan* t)
     t->nck = t->cycles + (t->rem > 0 ? 1 : 0);
     t->pk_max = 4 * (h - 1) * h * (2 * h - 1) / 6;  // sum_{j<h} (2j)^2: the largest recomputed footprint
     t->std_blocks = kStdAdjBlocks;
-    const size_t S = align_up(d.state_bytes);
+    const size_t S = align_up(d.state_bytes), SL = align_up(sizeof(double) * (size_t)nx * nx);
     t->ck_off = 0;
     t->pairs_off = t->ck_off + S * (size_t)t->nck;
-    t->stash_off = t->pairs_off + 6 * S;  // P0 P1 Q0 Q1 L0 L1
+    t->stash_off = t->pairs_off + 4 * S + 2 * SL;  // P0 P1 Q0 Q1 (state type), L0 L1 (lambda, double)
     t->part_off = t->stash_off + S * (size_t)t->rem;
     t->nparts = t->cycles * 4 * (int64_t)tiles * tiles + t->rem * kStdAdjBlocks;
     t->total = t->part_off + align_up(sizeof(double) * (size_t)(t->nparts + 1 + kAdjCombine));
@@ -438,13 +438,15 @@ int swept_adjoint(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes
     void* P1 = tape + t.pairs_off + S;
     void* Q0 = tape + t.pairs_off + 2 * S;
     void* Q1 = tape + t.pairs_off + 3 * S;
-    void* La = tape + t.pairs_off + 4 * S;  // lambda at the start of the next reverse step / cycle
-    void* Lb = tape + t.pairs_off + 5 * S;
+    const size_t SL = align_up(sizeof(double) * (size_t)c->prob.nx * c->prob.nx);
+    void* La = tape + t.pairs_off + 4 * S;  // lambda (double) at the start of the next reverse step / cycle
+    void* Lb = tape + t.pairs_off + 4 * S + SL;
     double* parts = reinterpret_cast<double*>(tape + t.part_off);
     const int N = c->prob.nx, tiles = N / c->d.tile, t2 = tiles * tiles, h = c->d.h;
     hipStream_t st = c->stream;
-    hipError_t e = hipMemcpyAsync(La, d_gTM, SB, hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "adjoint init copy");
+    const size_t NN = (size_t)N * N;
+    hipError_t e = swept::launch_lambda_convert(c->prob.dtype, d_gTM, La, NN, true, st);
+    if (e != hipSuccess) return hip_fail(e, "adjoint seed");
     int64_t pslot = 0;
     if (t.rem > 0) {  // the last rem steps: forward levels into the stash, then one adjoint step per level
         char* stash = tape + t.stash_off;
@@ -498,7 +500,7 @@ int swept_adjoint(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes
             Lb = tmp;
         }
     }
-    e = hipMemcpyAsync(d_gT0, La, SB, hipMemcpyDeviceToDevice, st);
+    e = swept::launch_lambda_convert(c->prob.dtype, La, d_gT0, NN, false, st);
     if (e == hipSuccess)
         e = swept::launch_plane_sums(0, parts, 1, (size_t)pslot, parts + t.nparts + 1, kAdjCombine, parts + t.nparts,
                                      st);

@@ -59,7 +59,7 @@ def test_adjoint_fp32_states_error():
     ref, dJdr = oracle.heat_adjoint(T0, g, r, steps)
     e = rel_err(gT0, ref)
     print(f"FP32 adjoint vs FP64 oracle: dJ/dT0 {e:.2e}, dJ/dalpha {abs(dalpha - dJdr * r) / abs(dJdr * r):.2e}")
-    assert e < 1e-5 and abs(dalpha - dJdr * r) < 1e-5 * abs(dJdr * r)
+    assert e < 1e-6 and abs(dalpha - dJdr * r) < 1e-6 * abs(dJdr * r)
 
 
 def test_transpose_identity_on_gpu():
@@ -139,15 +139,15 @@ def _c3_fd(T0n, Tsn, dt, steps, tile, seed):
 
 
 def test_c3_gradients_vs_fd_and_time():
-    """1024^2, r = 0.2, 2000 steps, tile 32 (checkpoint per cycle of 16 steps).  FP64 state:
-    directional derivative in T0 and dJ/dalpha within 1e-6 of FP64 central differences.  FP32
-    state (the configuration's precision): the same comparison gives the FP32 floor, stated and
-    bounded by 1e-5.  The adjoint takes at most 3x the checkpointed forward's time."""
+    """1024^2, r = 0.2, 2000 steps, tile 32 (checkpoint per cycle of 16 steps).  FP64 and FP32
+    state (FP32 is the configuration's precision; lambda is carried in FP64 in both): the
+    directional derivative in T0 and dJ/dalpha within 1e-6 of FP64 central differences.  The
+    adjoint takes at most 3x the checkpointed forward's time."""
     steps, tile = 2000, 32
     T0n, Tsn, dt, g64, ga64, tf64, ta64 = _c3_run(torch.float64)
     _, _, _, g32, ga32, tf32, ta32 = _c3_run(torch.float32)
     v, fdv, fda = _c3_fd(T0n, Tsn, dt, steps, tile, 1)
-    for name, g, ga, tol in (("fp64", g64, ga64, 1e-6), ("fp32", g32, ga32, 1e-5)):
+    for name, g, ga, tol in (("fp64", g64, ga64, 1e-6), ("fp32", g32, ga32, 1e-6)):
         ad = float(np.sum(g * v))
         ev, ea = abs(ad - fdv) / abs(fdv), abs(ga - fda) / abs(fda)
         print(f"C3 {name}: dJ/dT0.v rel {ev:.2e}, dJ/dalpha rel {ea:.2e}")
