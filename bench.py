@@ -16,7 +16,8 @@ and the CPU oracle timed on a bounded sample of the same workload.
 Other workloads (--workload): euler (2048^2 vortex, 500 RK2 steps per
 step), adjoint (1024^2 FP32 heat, 2000 steps: forward with checkpoints +
 reverse sweep per step), batch (48 heat + 16 Euler problems, FP32, 200 steps,
-one persistent launch per step).
+one persistent launch per step), study (the paper's parameter study at a
+GPU share of 100%: speedup over array sizes 320-1120 and block sizes 8-32).
 
 Usage: python bench.py [--steps K] [--warmup W] [--dtype f64|f32] [--tile B] [--workload W]
 """
@@ -74,7 +75,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["heat", "euler", "adjoint", "batch"], default="heat")
+    ap.add_argument("--workload", choices=["heat", "euler", "adjoint", "batch", "study"], default="heat")
     ap.add_argument("--dtype", choices=["f64", "f32"], default=None)
     ap.add_argument("--tile", type=int, default=0, help="0: tuned or default tile")
     ap.add_argument("--wg", type=int, default=0, help="0: tuned or library default")
@@ -209,6 +210,41 @@ def run_heat(args):
     return out
 
 
+def reductions(solver, q, S, n, calls=50):
+    """The two whole-state reductions on the Euler state: the CFL time step (max over cells)
+    and the FP64 conservation sums.  Both return host scalars, so each call synchronises;
+    the figure is the mean latency per call over back-to-back calls, and the rate counts the
+    one read of the 4 planes each makes."""
+    import ctypes
+
+    import torch
+
+    from paper_2105_10332_amd.solver import EULER, _dev_ptr, _stream_ptr, make_problem, swept_workspace_bytes
+    from paper_2105_10332_amd._lib import check, lib
+
+    prob = make_problem(EULER, n, q.dtype, 1.0, 10.0, gamma=1.4)
+    nbytes = swept_workspace_bytes(prob)
+    work = torch.empty(nbytes, dtype=torch.uint8, device=q.device)
+    out = ctypes.c_double(0.0)
+
+    def cfl():
+        check(lib().swept_cfl_dt(ctypes.byref(prob), _dev_ptr(q), 0.4, _dev_ptr(work), nbytes, _stream_ptr(),
+                                 ctypes.byref(out)))
+
+    res = {}
+    for name, fn in (("cfl_dt", cfl), ("conserved", solver.swept_conserved)):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(calls):
+            fn()
+        el = (time.perf_counter() - t) / calls
+        b = 4 * S * n * n
+        res[name] = {"us_per_call": el * 1e6, "bytes_read": b, "GBps": b / el / 1e9, "frac": b / el / 1e9 / HBM_PEAK_GBS,
+                     "note": "synchronous call: kernels + result copy + host wait"}
+    return res
+
+
 def run_euler(args):
     import numpy as np
     import torch
@@ -245,6 +281,7 @@ def run_euler(args):
         ssec, _ = timed(lambda: ss.standard_advance(M), 1)
         out["standard"] = {"value": n * n * M / ssec, "unit": "cell-steps/s", "ms_per_advance": ssec * 1e3}
         out["speedup_vs_standard"] = rate / out["standard"]["value"]
+    out["reductions"] = reductions(solver, q, S, n)
     out["wall_s"] = wall
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_euler(np.float64 if dt_name == "f64" else np.float32, n, dt)
@@ -347,6 +384,87 @@ def run_batch(args):
     return out
 
 
+STUDY_SIZES = (320, 480, 640, 800, 960, 1120)  # array edges of the paper's parameter study (Sec. 4)
+STUDY_TILES = (8, 12, 16, 24, 32)                # its block sizes
+
+
+def run_study(args):
+    """The paper's one-node parameter study at a GPU share of 100%: speedup S = R_standard /
+    R_swept (Sec. 4) over its array sizes and block sizes, heat and Euler, 500 time steps.
+    Pairs the library rejects (N % b != 0, LDS) are left out.  For each (kind, N, b) the
+    workgroup size is the fastest of 64/128/256 on one advance; then swept and Standard are
+    each timed over args.steps advances."""
+    import math
+
+    import torch
+
+    from paper_2105_10332_amd import _lib, problems
+    from paper_2105_10332_amd.solver import EULER, HEAT, SweptSolver, swept_cfl_dt, swept_workspace_bytes, make_problem
+
+    dt_name = args.dtype or "f64"
+    tdt = torch.float64 if dt_name == "f64" else torch.float32
+    M = args.advance_steps or 500
+    k = max(1, args.steps)
+    table, logs = {"heat": {}, "euler": {}}, []
+    t_all = time.perf_counter()
+    for kind in ("heat", "euler"):
+        for n in STUDY_SIZES:
+            if kind == "heat":
+                x0 = torch.tensor(problems.heat_fourier_modes(n), dtype=tdt, device="cuda")
+                dt, L, code = 0.2 / n / n, 1.0, HEAT
+            else:
+                q64 = torch.tensor(problems.shu_vortex(n), device="cuda")
+                dt, L, code = swept_cfl_dt(q64, 10.0, 0.4), 10.0, EULER
+                x0 = q64.to(tdt)
+            row = {}
+            std = None
+            for b in STUDY_TILES:
+                try:
+                    swept_workspace_bytes(make_problem(code, n, tdt, dt, L, 1.0, 1.4), b, 0)
+                except _lib.SweptError:
+                    continue
+                best = None
+                for wg in (64, 128, 256):
+                    st = x0.clone()
+                    sv = SweptSolver(code, st, dt=dt, length=L, alpha=1.0, gamma=1.4, tile=b, wg=wg)
+                    sv.swept_advance(M)
+                    sec, _ = timed(lambda: sv.swept_advance(M), 1)
+                    if best is None or sec < best[0]:
+                        best = (sec, wg)
+                    sv.close()
+                st = x0.clone()
+                sv = SweptSolver(code, st, dt=dt, length=L, alpha=1.0, gamma=1.4, tile=b, wg=best[1])
+                sv.swept_advance(M)
+                sw, _ = timed(lambda: sv.swept_advance(M), k)
+                if std is None:
+                    sv.standard_advance(M)
+                    std, _ = timed(lambda: sv.standard_advance(M), k)
+                sv.close()
+                row[b] = {"S": std / sw, "swept_ms": sw / k * 1e3, "wg": best[1]}
+            for b in row:
+                row[b]["standard_ms"] = std / k * 1e3
+            table[kind][n] = row
+            logs.append(f"{kind} {n}: " + ", ".join(f"b{b} S={v['S']:.2f}" for b, v in row.items()))
+            print(logs[-1], file=sys.stderr, flush=True)
+    heat_s = [v["S"] for row in table["heat"].values() for v in row.values()]
+    euler_s = [v["S"] for row in table["euler"].values() for v in row.values()]
+    gmean = math.exp(sum(math.log(v) for v in heat_s) / len(heat_s))
+
+    def best_of(kind):
+        return {n: max(row.items(), key=lambda kv: kv[1]["S"])[0] for n, row in table[kind].items()}
+
+    cfg = {"workload": f"parameter study: heat (r=0.2, 16 Fourier modes) and Euler (vortex eps 5, CFL 0.4) on "
+                       f"N x N, N in {list(STUDY_SIZES)}, block sizes {list(STUDY_TILES)} where valid, {M} steps, "
+                       f"GPU share 100%", "sizes": list(STUDY_SIZES), "tiles": list(STUDY_TILES)}
+    out = base_record(args, gmean, "x (Standard time / Swept time, geometric mean over heat cases)",
+                      time.perf_counter() - t_all, dt_name, cfg)
+    out["ms_per_step"] = None
+    out["table"] = table
+    out["range"] = {"heat": [min(heat_s), max(heat_s)], "euler": [min(euler_s), max(euler_s)]}
+    out["best_tile"] = {"heat": best_of("heat"), "euler": best_of("euler")}
+    return out
+
+
 def copy_reference(n: int = 4096, reps: int = 3):
     """A plain device-to-device copy of one n x n FP64 state, reps times: the known-size
     traffic that scales the HBM counters of the profiles."""
@@ -369,7 +487,8 @@ def main():
     if args.copy_reference:
         copy_reference()
         return
-    fn = {"heat": run_heat, "euler": run_euler, "adjoint": run_adjoint, "batch": run_batch}[args.workload]
+    fn = {"heat": run_heat, "euler": run_euler, "adjoint": run_adjoint, "batch": run_batch,
+          "study": run_study}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 
