@@ -39,7 +39,7 @@ METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB
 # WRITE_SIZE x 1.0: the factors a plain copy of known size reads), keyed by workload and launch
 # shape, valid only for the kernel sources whose hash is recorded with it (null otherwise).
 MEASURED_TRAFFIC = {
-    ("heat", "f64", 4096, 64, 512, 1000): (629.5e6, "53d1d28585f4c2a0"),
+    ("heat", "f64", 4096, 64, 512, 1000): (628.2e6, "ee94bec16704e261"),
 }
 KERNEL_SOURCES = ("scheme.h", "device_common.h", "kernels.hip", "launch.h")
 
@@ -80,6 +80,8 @@ def parse():
     ap.add_argument("--tile", type=int, default=0, help="0: tuned or default tile")
     ap.add_argument("--wg", type=int, default=0, help="0: tuned or library default")
     ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--scheme", type=int, default=0,
+                    help="Euler scheme variant bits: 1 limiter factors as printed, 2 Roe-averaged speed")
     ap.add_argument("--advance-steps", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-standard", action="store_true")
@@ -131,20 +133,20 @@ def cpu_heat(dtype_np, n, r, budget_s=25.0):
                       f"(OpenMP over rows), {el:.1f} s"}
 
 
-def cpu_euler(dtype_np, n, dt, budget_s=15.0):
+def cpu_euler(dtype_np, n, dt, budget_s=15.0, scheme=0):
     import numpy as np
 
     import oracle
     from paper_2105_10332_amd import problems
 
     Q0 = problems.shu_vortex(n).astype(dtype_np)
-    Q1 = oracle.euler_run(Q0, dt, 10 / n, 10 / n, 1.4, 1)
+    Q1 = oracle.euler_run(Q0, dt, 10 / n, 10 / n, 1.4, 1, scheme)
     t = time.perf_counter()
-    Q1 = oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, 2)
+    Q1 = oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, 2, scheme)
     one = (time.perf_counter() - t) / 2
     k = max(1, min(1000, int(budget_s / max(one, 1e-6))))
     t = time.perf_counter()
-    oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, k)
+    oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, k, scheme)
     el = time.perf_counter() - t
     return {"value": n * n * k / el, "unit": "cell-steps/s", "cores": cores(), "kind": "oracle",
             "sample": f"Euler vortex {n}x{n} {np.dtype(dtype_np).name}, {k} RK2 steps of the C oracle, {el:.1f} s"}
@@ -261,22 +263,24 @@ def run_euler(args):
     Q0 = problems.shu_vortex(n)
     q = torch.tensor(Q0, dtype=tdt, device="cuda")
     dt = swept_cfl_dt(torch.tensor(Q0, device="cuda"), 10.0, 0.4)
-    solver = SweptSolver(EULER, q, dt=dt, length=10.0, gamma=1.4, tile=tile, wg=wg)
+    solver = SweptSolver(EULER, q, dt=dt, length=10.0, gamma=1.4, tile=tile, wg=wg, scheme=args.scheme)
     for _ in range(args.warmup):
         solver.swept_advance(M)
     sec, wall = timed(lambda: solver.swept_advance(M), args.steps)
     cells = n * n * M * args.steps
     rate = cells / sec
     plan = geometry.totals(n, tile, 2, 2 * M, True)
-    cfg = {"workload": f"Euler {n}x{n} periodic [0,10]^2, gamma 1.4, vortex eps 5 on (1,1), minmod + Rusanov, "
+    scheme = {0: "minmod + Rusanov", 1: "limiter factors as printed + Rusanov", 2: "minmod + Roe-averaged speed",
+              3: "limiter factors as printed + Roe-averaged speed"}[args.scheme]
+    cfg = {"workload": f"Euler {n}x{n} periodic [0,10]^2, gamma 1.4, vortex eps 5 on (1,1), {scheme}, "
                        f"RK2, CFL 0.4 (dt {dt:.6e}), {M} steps per bench step; swept tile {tile}",
-           "tile": tile, "time_steps_per_step": M, "launches_per_step": plan["launches"]}
+           "tile": tile, "scheme": args.scheme, "time_steps_per_step": M, "launches_per_step": plan["launches"]}
     out = base_record(args, rate, "cell-steps/s", sec, dt_name, cfg)
     out["effective_GBps"] = 8 * S * cells / sec / 1e9
     out["roofline"] = roofline(plan, S, 4, plan["launches"] * args.steps, sec, "swept_phase_kernel<EulerS>")
     if not args.no_standard:
         st = torch.tensor(Q0, dtype=tdt, device="cuda")
-        ss = SweptSolver(EULER, st, dt=dt, length=10.0, gamma=1.4, tile=tile)
+        ss = SweptSolver(EULER, st, dt=dt, length=10.0, gamma=1.4, tile=tile, scheme=args.scheme)
         ss.standard_advance(M)
         ssec, _ = timed(lambda: ss.standard_advance(M), 1)
         out["standard"] = {"value": n * n * M / ssec, "unit": "cell-steps/s", "ms_per_advance": ssec * 1e3}
@@ -284,7 +288,7 @@ def run_euler(args):
     out["reductions"] = reductions(solver, q, S, n)
     out["wall_s"] = wall
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_euler(np.float64 if dt_name == "f64" else np.float32, n, dt)
+        out["cpu_baseline"] = cpu_euler(np.float64 if dt_name == "f64" else np.float32, n, dt, scheme=args.scheme)
     return out
 
 
@@ -392,8 +396,8 @@ def run_study(args):
     """The paper's one-node parameter study at a GPU share of 100%: speedup S = R_standard /
     R_swept (Sec. 4) over its array sizes and block sizes, heat and Euler, 500 time steps.
     Pairs the library rejects (N % b != 0, LDS) are left out.  For each (kind, N, b) the
-    workgroup size is the fastest of 64/128/256 on one advance; then swept and Standard are
-    each timed over args.steps advances."""
+    workgroup size is the fastest of 64 ... 1024 (heat) or 64 ... 256 (Euler) on one advance;
+    then swept and Standard are each timed over args.steps advances."""
     import math
 
     import torch
@@ -424,7 +428,7 @@ def run_study(args):
                 except _lib.SweptError:
                     continue
                 best = None
-                for wg in (64, 128, 256):
+                for wg in ((64, 128, 256, 512, 1024) if kind == "heat" else (64, 128, 256)):
                     st = x0.clone()
                     sv = SweptSolver(code, st, dt=dt, length=L, alpha=1.0, gamma=1.4, tile=b, wg=wg)
                     sv.swept_advance(M)

@@ -77,7 +77,21 @@ typedef struct {
     double dt;      /* time step (> 0)                                        */
     double alpha;   /* heat diffusivity; r = alpha*dt/dx^2 with dx = lx/nx    */
     double gamma;   /* Euler ratio of specific heats (> 1)                    */
+    int32_t scheme; /* Euler scheme variant bits (0 for heat), see below       */
+    int32_t reserved; /* must be 0                                             */
 } swept_problem;
+
+/* Euler scheme variants (App. B prints the limiter and the spectral radius
+ * ambiguously).  0: pressure-ratio minmod face states, Q_L = Q_i +
+ * min(1/r_i,1)/2 (Q_{i+1}-Q_i) and Q_R = Q_{i+1} + min(r_{i+1},1)/2
+ * (Q_i-Q_{i+1}) with r_i = (p_{i+1}-p_i)/(p_i-p_{i-1}) (first order where
+ * r_i is not in (0, inf)), and the Rusanov speed s = max(|u_L|+c_L,
+ * |u_R|+c_R).  SWEPT_LIMITER_LITERAL takes the factors with the exponents as
+ * printed, min(r_i,1)/2 and min(1/r_{i+1},1)/2.  SWEPT_SPEED_ROE takes s =
+ * |u~|+c~ at the Roe-averaged state of Q_L and Q_R.  Bits combine.  The
+ * single-problem calls accept every combination; the batch accepts 0 only. */
+#define SWEPT_LIMITER_LITERAL 1
+#define SWEPT_SPEED_ROE 2
 
 /* Launch tuning.  tile = block size b of Sec. 3.2 (0: library default);
  * wg = threads per workgroup (0: 256; a multiple of 64, at most 1024 for heat,

@@ -71,13 +71,14 @@ def _declare(L):
         getattr(L, "oracle_heat_adjoint" + s).argtypes = [_P, _P, _P, ctypes.POINTER(_D), _I, _D, _I, _P, _P]
         getattr(L, "oracle_l2_mismatch" + s).argtypes = [_P, _P, _I]
         getattr(L, "oracle_l2_mismatch" + s).restype = _D
-        getattr(L, "oracle_euler_run" + s).argtypes = [_P, _P, _I, _D, _D, _D, _D, _I]
+        getattr(L, "oracle_euler_run" + s).argtypes = [_P, _P, _I, _D, _D, _D, _D, _I, _I]
         getattr(L, "oracle_euler_work_values" + s).argtypes = [_I]
         getattr(L, "oracle_euler_work_values" + s).restype = _I
         getattr(L, "oracle_cfl_dt" + s).argtypes = [_P, _I, _D, _D, _D, _D]
         getattr(L, "oracle_cfl_dt" + s).restype = _D
         getattr(L, "oracle_plane_sums" + s).argtypes = [_P, _I, _I, _P]
-        getattr(L, "oracle_face" + s).argtypes = [_P, _P, _P, _P, _I, _D, _P, _P, _P]
+        getattr(L, "oracle_face" + s).argtypes = [_P, _P, _P, _P, _I, _D, _I, _P, _P, _P]
+        getattr(L, "oracle_roe_average" + s).argtypes = [_P, _P, _I, _D, _P]
 
 
 def _sfx(a: np.ndarray) -> str:
@@ -130,15 +131,19 @@ def l2_mismatch(T: np.ndarray, Tstar: np.ndarray) -> float:
     return getattr(lib(), "oracle_l2_mismatch" + _sfx(T))(_ptr(T), _ptr(Tstar), T.size)
 
 
-def euler_run(Q0: np.ndarray, dt: float, dx: float, dy: float, gamma: float, steps: int) -> np.ndarray:
-    """``steps`` RK2 steps of the 2D Euler equations; Q0 is (4, N, N)."""
+LIMITER_LITERAL, SPEED_ROE = 1, 2  # scheme variant bits (see oracle.c)
+
+
+def euler_run(Q0: np.ndarray, dt: float, dx: float, dy: float, gamma: float, steps: int,
+              scheme: int = 0) -> np.ndarray:
+    """``steps`` RK2 steps of the 2D Euler equations; Q0 is (4, N, N); scheme = variant bits."""
     Q = np.array(Q0, copy=True, order="C")
     N = Q.shape[1]
     s = _sfx(Q)
     nwork = getattr(lib(), "oracle_euler_work_values" + s)(N)
     work = np.empty(nwork, dtype=Q.dtype)
     getattr(lib(), "oracle_euler_run" + s)(_ptr(Q), _ptr(work), N, float(dt), float(dx), float(dy),
-                                           float(gamma), int(steps))
+                                           float(gamma), int(steps), int(scheme))
     return Q
 
 
@@ -159,16 +164,25 @@ def plane_sums(Q: np.ndarray) -> np.ndarray:
     return out
 
 
-def face(A, B, C, D, axis: int, gamma: float, dtype=np.float64):
+def face(A, B, C, D, axis: int, gamma: float, dtype=np.float64, scheme: int = 0):
     """Reconstructed left/right states and numerical flux at the face between B and C.
 
     A..D are conserved 4-vectors of consecutive cells along the face normal;
-    axis 1 = x face (F), 2 = y face (G).  Returns (Q_L, Q_R, flux).
+    axis 1 = x face (F), 2 = y face (G); scheme = variant bits.  Returns (Q_L, Q_R, flux).
     """
     arrs = [np.ascontiguousarray(v, dtype=dtype) for v in (A, B, C, D)]
     L = np.empty(4, dtype=dtype)
     R = np.empty(4, dtype=dtype)
     F = np.empty(4, dtype=dtype)
-    getattr(lib(), "oracle_face" + _sfx(arrs[0]))(*[_ptr(a) for a in arrs], int(axis), float(gamma), _ptr(L),
-                                                 _ptr(R), _ptr(F))
+    getattr(lib(), "oracle_face" + _sfx(arrs[0]))(*[_ptr(a) for a in arrs], int(axis), float(gamma), int(scheme),
+                                                 _ptr(L), _ptr(R), _ptr(F))
     return L, R, F
+
+
+def roe_average(L, R, axis: int, gamma: float, dtype=np.float64):
+    """(u~_a, u~_b, H~, |u~_a| + c~) of the Roe average of two conserved 4-vectors along axis a."""
+    l = np.ascontiguousarray(L, dtype=dtype)
+    r = np.ascontiguousarray(R, dtype=dtype)
+    out = np.empty(4, dtype=dtype)
+    getattr(lib(), "oracle_roe_average" + _sfx(l))(_ptr(l), _ptr(r), int(axis), float(gamma), _ptr(out))
+    return out

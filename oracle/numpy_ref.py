@@ -65,8 +65,24 @@ def _phys_flux(Q, a, gamma, gm1):
     return F, np.abs(ua) + c
 
 
-def _face_flux(Q, axis, gamma):
-    """Flux through the face between each cell and its +axis neighbour."""
+def _roe_speed(L, R, a, gm1):
+    """|u~_a| + c~ at the sqrt(rho)-weighted (Roe) average of the face states L and R."""
+    b = 2 if a == 1 else 1
+    t = L.dtype.type
+    wl, wr = np.sqrt(L[0]), np.sqrt(R[0])
+    ual, ubl = L[a] / L[0], L[b] / L[0]
+    uar, ubr = R[a] / R[0], R[b] / R[0]
+    hl = (L[3] + _pressure(L, gm1)) / L[0]
+    hr = (R[3] + _pressure(R, gm1)) / R[0]
+    ua = (wl * ual + wr * uar) / (wl + wr)
+    ub = (wl * ubl + wr * ubr) / (wl + wr)
+    H = (wl * hl + wr * hr) / (wl + wr)
+    return np.abs(ua) + np.sqrt(gm1 * (H - t(0.5) * (ua * ua + ub * ub)))
+
+
+def _face_flux(Q, axis, gamma, scheme=0):
+    """Flux through the face between each cell and its +axis neighbour (scheme: variant bits,
+    1 = limiter exponents as printed, 2 = spectral radius at the Roe average)."""
     t = Q.dtype.type
     gm1 = gamma - t(1)
     a = 1 if axis == "x" else 2
@@ -78,34 +94,37 @@ def _face_flux(Q, axis, gamma):
         rC = shift(ratio, 1)
         okB = (rB > 0) & (rB < np.inf)
         okC = (rC > 0) & (rC < np.inf)
-        inv = t(1) / rB
-        phiL = t(0.5) * np.minimum(inv, t(1))
-        phiR = t(0.5) * np.minimum(rC, t(1))
+        if scheme & 1:
+            phiL = t(0.5) * np.minimum(rB, t(1))
+            phiR = t(0.5) * np.minimum(t(1) / rC, t(1))
+        else:
+            phiL = t(0.5) * np.minimum(t(1) / rB, t(1))
+            phiR = t(0.5) * np.minimum(rC, t(1))
     B = Q
     C = shift(Q, 1)
     L = np.where(okB[None], B + phiL[None] * (C - B), B)
     R = np.where(okC[None], C + phiR[None] * (B - C), C)
     fL, sL = _phys_flux(L, a, gamma, gm1)
     fR, sR = _phys_flux(R, a, gamma, gm1)
-    s = np.maximum(sL, sR)
+    s = _roe_speed(L, R, a, gm1) if scheme & 2 else np.maximum(sL, sR)
     return t(0.5) * ((fR + fL) + s[None] * (L - R))
 
 
-def euler_stage(Qbase, Qflux, hx, hy, gamma):
-    fx = _face_flux(Qflux, "x", gamma)
-    gy = _face_flux(Qflux, "y", gamma)
+def euler_stage(Qbase, Qflux, hx, hy, gamma, scheme=0):
+    fx = _face_flux(Qflux, "x", gamma, scheme)
+    gy = _face_flux(Qflux, "y", gamma, scheme)
     dF = fx - _sh(fx, -1, 0)
     dG = gy - _sh(gy, 0, -1)
     return (Qbase - hx * dF) - hy * dG
 
 
-def euler_run(Q0, dt, dx, dy, gamma, steps):
+def euler_run(Q0, dt, dx, dy, gamma, steps, scheme=0):
     Q = np.array(Q0, copy=True)
     t = Q.dtype.type
     g = t(gamma)
     hx, hy = t(0.5 * dt / dx), t(0.5 * dt / dy)
     kx, ky = t(dt / dx), t(dt / dy)
     for _ in range(steps):
-        Qs = euler_stage(Q, Q, hx, hy, g)
-        Q = euler_stage(Q, Qs, kx, ky, g)
+        Qs = euler_stage(Q, Q, hx, hy, g, scheme)
+        Q = euler_stage(Q, Qs, kx, ky, g, scheme)
     return Q

@@ -189,62 +189,114 @@ static inline void phys_flux(state4 q, int a, int b, REAL gamma, REAL gm1, REAL 
 
 static inline int ratio_ok(REAL r) { return r > (REAL)0 && r < (REAL)INFINITY; }
 
+/* Scheme variants (App. B leaves two things open; the default is the
+ * reading stated at the top of this file):
+ *   SCHEME_LIMITER_LITERAL: the limiter factors with the exponents exactly
+ *     as printed, min(r_i, 1)/2 for the left state and min(1/r_{i+1}, 1)/2
+ *     for the right one (each still used only for a ratio in (0, inf));
+ *   SCHEME_SPEED_ROE: the spectral radius of the flux Jacobian evaluated at
+ *     the Roe-averaged state of the two face states, |u~| + c~, in place of
+ *     the larger of the two one-sided speeds.  The bits combine. */
+#define SCHEME_LIMITER_LITERAL 1
+#define SCHEME_SPEED_ROE 2
+
+/* Roe average of face states L and R for the direction whose momentum is
+ * component a (other momentum b): weights sqrt(rho_L), sqrt(rho_R) applied
+ * to u_a, u_b and the total enthalpy H = (E + p)/rho.  out = (u~_a, u~_b,
+ * H~, |u~_a| + c~) with c~^2 = (gamma - 1)(H~ - (u~_a^2 + u~_b^2)/2); the
+ * Roe matrix of the x-split Euler flux has eigenvalues u~_a - c~, u~_a
+ * (twice) and u~_a + c~, so the last entry is its spectral radius. */
+static void roe_average(state4 L, state4 R, int a, int b, REAL gm1, REAL out[4])
+{
+    const REAL wl = (REAL)sqrt((double)L.v[0]), wr = (REAL)sqrt((double)R.v[0]);
+    const REAL ual = L.v[a] / L.v[0], ubl = L.v[b] / L.v[0];
+    const REAL uar = R.v[a] / R.v[0], ubr = R.v[b] / R.v[0];
+    const REAL pl = pressure(L, gm1), pr = pressure(R, gm1);
+    const REAL hl = (L.v[3] + pl) / L.v[0], hr = (R.v[3] + pr) / R.v[0];
+    const REAL ua = (wl * ual + wr * uar) / (wl + wr);
+    const REAL ub = (wl * ubl + wr * ubr) / (wl + wr);
+    const REAL H = (wl * hl + wr * hr) / (wl + wr);
+    const REAL c2 = gm1 * (H - (REAL)0.5 * (ua * ua + ub * ub));
+    out[0] = ua;
+    out[1] = ub;
+    out[2] = H;
+    out[3] = (REAL)fabs((double)ua) + (REAL)sqrt((double)c2);
+}
+
 /* Numerical flux through the face between cells B and C of the 1D run
- * A, B, C, D (App. B: pressure-ratio minmod reconstruction, then the
- * Rusanov-form flux).  a selects the normal momentum component. */
-static void face_flux_states(state4 A, state4 B, state4 C, state4 D, int a, REAL gamma, REAL out[4],
+ * A, B, C, D (App. B: pressure-ratio reconstruction, then the Rusanov-form
+ * flux).  a selects the normal momentum component; scheme the variant bits. */
+static void face_flux_states(state4 A, state4 B, state4 C, state4 D, int a, REAL gamma, int scheme, REAL out[4],
                              state4* Lo, state4* Ro)
 {
     const REAL gm1 = gamma - (REAL)1;
     const int b = (a == 1) ? 2 : 1;
+    const int literal = (scheme & SCHEME_LIMITER_LITERAL) != 0;
     const REAL pA = pressure(A, gm1), pB = pressure(B, gm1), pC = pressure(C, gm1), pD = pressure(D, gm1);
     const REAL rB = (pC - pB) / (pB - pA); /* ratio at the left cell  */
     const REAL rC = (pD - pC) / (pC - pB); /* ratio at the right cell */
     state4 L = B, R = C;
     if (ratio_ok(rB)) {
-        const REAL inv = (REAL)1 / rB;
-        const REAL phi = (REAL)0.5 * (inv < (REAL)1 ? inv : (REAL)1);
+        /* minmod reading: min(1/r_B, 1); as printed: min(r_B, 1) */
+        const REAL e = literal ? rB : (REAL)1 / rB;
+        const REAL phi = (REAL)0.5 * (e < (REAL)1 ? e : (REAL)1);
         for (int c = 0; c < 4; ++c) L.v[c] = B.v[c] + phi * (C.v[c] - B.v[c]);
     }
     if (ratio_ok(rC)) {
-        const REAL phi = (REAL)0.5 * (rC < (REAL)1 ? rC : (REAL)1);
+        /* minmod reading: min(r_C, 1); as printed: min(1/r_C, 1) */
+        const REAL e = literal ? (REAL)1 / rC : rC;
+        const REAL phi = (REAL)0.5 * (e < (REAL)1 ? e : (REAL)1);
         for (int c = 0; c < 4; ++c) R.v[c] = C.v[c] + phi * (B.v[c] - C.v[c]);
     }
     REAL fL[4], fR[4], sL, sR;
     phys_flux(L, a, b, gamma, gm1, fL, &sL);
     phys_flux(R, a, b, gamma, gm1, fR, &sR);
-    const REAL s = sL > sR ? sL : sR;
+    REAL s = sL > sR ? sL : sR;
+    if (scheme & SCHEME_SPEED_ROE) {
+        REAL roe[4];
+        roe_average(L, R, a, b, gm1, roe);
+        s = roe[3];
+    }
     for (int c = 0; c < 4; ++c) out[c] = (REAL)0.5 * ((fR[c] + fL[c]) + s * (L.v[c] - R.v[c]));
     if (Lo) *Lo = L;
     if (Ro) *Ro = R;
 }
 
-static void face_flux(state4 A, state4 B, state4 C, state4 D, int a, REAL gamma, REAL out[4])
+static void face_flux(state4 A, state4 B, state4 C, state4 D, int a, REAL gamma, int scheme, REAL out[4])
 {
-    face_flux_states(A, B, C, D, a, gamma, out, 0, 0);
+    face_flux_states(A, B, C, D, a, gamma, scheme, out, 0, 0);
 }
 
 /* The reconstructed face states and the numerical flux through the face
  * between cells B and C of the run A, B, C, D (each a 4-vector of conserved
- * variables); a = 1 for an x face, 2 for a y face.  Exposed for unit checks
- * of the limiter and flux against their textbook forms. */
+ * variables); a = 1 for an x face, 2 for a y face; scheme the variant bits.
+ * Exposed for unit checks of the limiter and flux against their textbook
+ * forms. */
 void NAME(oracle_face)(const REAL* A, const REAL* B, const REAL* C, const REAL* D, int64_t a, double gamma,
-                       REAL* Lout, REAL* Rout, REAL* Fout)
+                       int64_t scheme, REAL* Lout, REAL* Rout, REAL* Fout)
 {
     state4 s[4];
     const REAL* in[4] = {A, B, C, D};
     for (int k = 0; k < 4; ++k)
         for (int c = 0; c < 4; ++c) s[k].v[c] = in[k][c];
     state4 L, R;
-    face_flux_states(s[0], s[1], s[2], s[3], (int)a, (REAL)gamma, Fout, &L, &R);
+    face_flux_states(s[0], s[1], s[2], s[3], (int)a, (REAL)gamma, (int)scheme, Fout, &L, &R);
     for (int c = 0; c < 4; ++c) { Lout[c] = L.v[c]; Rout[c] = R.v[c]; }
+}
+
+/* Roe average of two states (see roe_average), exposed for unit checks. */
+void NAME(oracle_roe_average)(const REAL* L, const REAL* R, int64_t a, double gamma, REAL* out)
+{
+    state4 l, r;
+    for (int c = 0; c < 4; ++c) { l.v[c] = L[c]; r.v[c] = R[c]; }
+    roe_average(l, r, (int)a, a == 1 ? 2 : 1, (REAL)gamma - (REAL)1, out);
 }
 
 /* One RK stage: Qout = Qbase - hx (Fx_{i+1/2} - Fx_{i-1/2}) - hy (Gy_{j+1/2} - Gy_{j-1/2}),
  * fluxes evaluated on Qflux.  Face fluxes are computed once per face into
  * fx / gy (each 4*N*N), so the two cells sharing a face use the same value. */
 static void euler_stage(const REAL* Qbase, const REAL* Qflux, REAL* Qout, int64_t N, REAL hx, REAL hy,
-                        REAL gamma, REAL* fx, REAL* gy)
+                        REAL gamma, int scheme, REAL* fx, REAL* gy)
 {
     const int64_t NN = N * N;
 #pragma omp parallel for schedule(static)
@@ -254,12 +306,12 @@ static void euler_stage(const REAL* Qbase, const REAL* Qflux, REAL* Qout, int64_
             /* x face i+1/2 of row j: cells i-1, i, i+1, i+2 */
             face_flux(load4(Qflux, NN, j * N + wrap(i - 1, N)), load4(Qflux, NN, j * N + i),
                       load4(Qflux, NN, j * N + wrap(i + 1, N)), load4(Qflux, NN, j * N + wrap(i + 2, N)), 1,
-                      gamma, f);
+                      gamma, scheme, f);
             for (int c = 0; c < 4; ++c) fx[c * NN + j * N + i] = f[c];
             /* y face j+1/2 of column i: rows j-1, j, j+1, j+2 */
             face_flux(load4(Qflux, NN, wrap(j - 1, N) * N + i), load4(Qflux, NN, j * N + i),
                       load4(Qflux, NN, wrap(j + 1, N) * N + i), load4(Qflux, NN, wrap(j + 2, N) * N + i), 2,
-                      gamma, f);
+                      gamma, scheme, f);
             for (int c = 0; c < 4; ++c) gy[c * NN + j * N + i] = f[c];
         }
     }
@@ -278,9 +330,10 @@ static void euler_stage(const REAL* Qbase, const REAL* Qflux, REAL* Qout, int64_
 
 /* M explicit-midpoint RK2 steps of the 2D Euler equations on an N x N
  * periodic grid with spacings dx, dy.  Q (4*N*N) holds Q^0 on entry and
- * Q^M on exit; work must hold 16*N*N values (Q*, Q^{n+1}, face fluxes). */
+ * Q^M on exit; work must hold 16*N*N values (Q*, Q^{n+1}, face fluxes);
+ * scheme = variant bits (0: minmod + Rusanov). */
 void NAME(oracle_euler_run)(REAL* Q, REAL* work, int64_t N, double dt, double dx, double dy, double gamma_in,
-                            int64_t M)
+                            int64_t M, int64_t scheme)
 {
     const int64_t NN = N * N;
     REAL* qs = work;
@@ -291,8 +344,8 @@ void NAME(oracle_euler_run)(REAL* Q, REAL* work, int64_t N, double dt, double dx
     const REAL hx = (REAL)(0.5 * dt / dx), hy = (REAL)(0.5 * dt / dy);
     const REAL kx = (REAL)(dt / dx), ky = (REAL)(dt / dy);
     for (int64_t m = 0; m < M; ++m) {
-        euler_stage(Q, Q, qs, N, hx, hy, gamma, fx, gy);
-        euler_stage(Q, qs, qn, N, kx, ky, gamma, fx, gy);
+        euler_stage(Q, Q, qs, N, hx, hy, gamma, (int)scheme, fx, gy);
+        euler_stage(Q, qs, qn, N, kx, ky, gamma, (int)scheme, fx, gy);
         memcpy(Q, qn, (size_t)(4 * NN) * sizeof(REAL));
     }
 }

@@ -20,6 +20,7 @@ ERRORS = {
 CODES = {v: k for k, v in ERRORS.items()}
 HEAT, EULER = 0, 1
 F64, F32 = 0, 1
+LIMITER_LITERAL, SPEED_ROE = 1, 2  # Euler scheme variant bits (swept.h)
 
 
 class SweptError(RuntimeError):
@@ -32,7 +33,8 @@ class SweptError(RuntimeError):
 class Problem(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("nx", ctypes.c_int32),
                 ("ny", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
-                ("dt", ctypes.c_double), ("alpha", ctypes.c_double), ("gamma", ctypes.c_double)]
+                ("dt", ctypes.c_double), ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("scheme", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Tuning(ctypes.Structure):

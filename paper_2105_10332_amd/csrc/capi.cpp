@@ -85,6 +85,10 @@ int derive(const swept_problem* p, const swept_tuning* t, Derived* d)
     if (!(p->lx > 0) || !(p->ly > 0) || !std::isfinite(p->lx) || !std::isfinite(p->ly))
         return fail(SWEPT_EINVAL, "domain lengths must be positive");
     if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(SWEPT_EUNSTABLE, "dt must be positive (dt=%g)", p->dt);
+    if (p->reserved != 0) return fail(SWEPT_EINVAL, "reserved field must be 0");
+    if (p->scheme & ~(SWEPT_LIMITER_LITERAL | SWEPT_SPEED_ROE))
+        return fail(SWEPT_EINVAL, "unknown scheme bits %d", p->scheme);
+    if (p->kind == SWEPT_HEAT && p->scheme != 0) return fail(SWEPT_EINVAL, "heat has no scheme variants");
     d->nvar = p->kind == SWEPT_HEAT ? 1 : 4;
     d->n = p->kind == SWEPT_HEAT ? 1 : 2;
     d->lps = p->kind == SWEPT_HEAT ? 1 : 2;
@@ -351,6 +355,7 @@ static swept::PhaseArgs phase_args(const swept_ctx* c, int L)
     a.tiles = c->prob.nx / c->d.tile;
     a.L = L;
     a.tab = c->tab_dev;
+    a.scheme = c->prob.scheme;
     for (int k = 0; k < 5; ++k) a.p[k] = c->c[k];
     return a;
 }
@@ -527,6 +532,7 @@ int standard_advance(swept_ctx* c, int64_t n_steps)
             swept::StdArgs a;
             a.N = c->prob.nx;
             a.ts = c->std_ts;
+            a.scheme = c->prob.scheme;
             for (int k = 0; k < 5; ++k) a.p[k] = c->c[k];
             e = swept::launch_euler_standard(c->prob.dtype, in, out, a, c->stream);
         }
@@ -624,6 +630,7 @@ int batch_derive(const swept_problem* probs, const swept_tuning* tunes, int32_t 
     size_t off = 0;
     for (int q = 0; q < count; ++q) {
         if (probs[q].dtype != probs[0].dtype) return fail(SWEPT_EINVAL, "all problems of a batch share one dtype");
+        if (probs[q].scheme != 0) return fail(SWEPT_ENOTSUP, "problem %d: the batch runs scheme 0 only", q);
         swept_tuning t{tunes ? tunes[q].tile : 0, swept::batch_wg(probs[0].dtype)};
         const int rc = derive(&probs[q], &t, &(*d)[q]);
         if (rc) return rc;

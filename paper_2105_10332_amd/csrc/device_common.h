@@ -25,11 +25,15 @@ __device__ __forceinline__ int wrapi(int g, int N)
 }
 
 struct HeatS {
-    static constexpr int NVAR = 1, R = 1, TWO_STAGE = 0, MAXWG = 1024;
+    static constexpr int NVAR = 1, R = 1, TWO_STAGE = 0, MAXWG = 1024, SCHEME = 0;
 };
-struct EulerS {  // register-heavy per-cell update: at most 512 threads (FP32) or 256 (FP64)
-    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 512;
+// Euler with scheme variant V (limiter and spectral-radius bits, scheme.h);
+// register-heavy per-cell update: at most 512 threads (FP32) or 256 (FP64)
+template <int V>
+struct EulerSV {
+    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 512, SCHEME = V;
 };
+using EulerS = EulerSV<0>;
 
 __device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
 {
@@ -177,7 +181,7 @@ __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>&
     }
 }
 
-template <typename T, class Store>
+template <typename T, int V, class Store>
 __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, T* __restrict__ pbuf,
                                             T* __restrict__ fbuf, int FS, int W, int P, int x0, int y0, int fw, int fh,
                                             bool second_stage, T gamma, T cx, T cy, const Store& store)
@@ -212,7 +216,7 @@ __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, 
                 qc[c] = prev[c * P + lb + 1];
                 qd[c] = prev[c * P + lb + 2];
             }
-            face_flux<T, 1>(qa, qb, qc, qd, pbuf[lb - 1], pbuf[lb], pbuf[lb + 1], pbuf[lb + 2], gamma, f);
+            face_flux<T, 1, V>(qa, qb, qc, qd, pbuf[lb - 1], pbuf[lb], pbuf[lb + 1], pbuf[lb + 2], gamma, f);
 #pragma unroll
             for (int c = 0; c < 4; ++c) fbuf[c * FS + i] = f[c];
         }
@@ -250,7 +254,7 @@ __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, 
                 qc[c] = prev[c * P + lb + W];
                 qd[c] = prev[c * P + lb + 2 * W];
             }
-            face_flux<T, 2>(qa, qb, qc, qd, pbuf[lb - W], pbuf[lb], pbuf[lb + W], pbuf[lb + 2 * W], gamma, f);
+            face_flux<T, 2, V>(qa, qb, qc, qd, pbuf[lb - W], pbuf[lb], pbuf[lb + W], pbuf[lb + 2 * W], gamma, f);
 #pragma unroll
             for (int c = 0; c < 4; ++c) fbuf[c * FS + i] = f[c];
         }
@@ -433,8 +437,8 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
             const int FS = (b + 1) * b;
             const bool second = (lvl & 1) == 0;
             const SweptStore<T, NVAR> st{gout, NN, N, ox, oy, C, hx2, hy2};
-            euler_level<T>(prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second, (T)a.p[0],
-                           (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]), st);
+            euler_level<T, S::SCHEME>(prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second, (T)a.p[0],
+                                      (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]), st);
         }
         __syncthreads();
     }

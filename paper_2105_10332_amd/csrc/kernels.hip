@@ -81,7 +81,7 @@ struct TileStore {
     }
 };
 
-template <typename T>
+template <typename T, int V>
 __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                              StdArgs a)
 {
@@ -104,11 +104,11 @@ __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict
     T* pbuf = lds + 2 * BUF;
     T* fbuf = pbuf + P;
     const T gamma = (T)a.p[0];
-    euler_level<T>(q0, q1, pbuf, fbuf, FS, W, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1], (T)a.p[2],
-                   NoStore{});
+    euler_level<T, V>(q0, q1, pbuf, fbuf, FS, W, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1], (T)a.p[2],
+                      NoStore{});
     __syncthreads();
     const TileStore<T> st{out, NN, N, tx0 - 4, ty0 - 4};
-    euler_level<T>(q1, q0, pbuf, fbuf, FS, W, P, 4, 4, TS, TS, true, gamma, (T)a.p[3], (T)a.p[4], st);
+    euler_level<T, V>(q1, q0, pbuf, fbuf, FS, W, P, 4, 4, TS, TS, true, gamma, (T)a.p[3], (T)a.p[4], st);
 }
 
 // --------------------------------------------------------------- reductions
@@ -203,10 +203,21 @@ static const void* phase_kernel(int tile)
     return (const void*)swept_phase_kernel<S, T, 0>;
 }
 
-static const void* phase_kernel(int kind, int dtype, int tile)
+template <int V>
+static const void* euler_phase_kernel(int dtype)
+{
+    return dtype == 0 ? phase_kernel<EulerSV<V>, double>(0) : phase_kernel<EulerSV<V>, float>(0);
+}
+
+static const void* phase_kernel(int kind, int dtype, int tile, int scheme)
 {
     if (kind == 0) return dtype == 0 ? phase_kernel<HeatS, double>(tile) : phase_kernel<HeatS, float>(tile);
-    return dtype == 0 ? phase_kernel<EulerS, double>(tile) : phase_kernel<EulerS, float>(tile);
+    switch (scheme) {
+        case 1: return euler_phase_kernel<1>(dtype);
+        case 2: return euler_phase_kernel<2>(dtype);
+        case 3: return euler_phase_kernel<3>(dtype);
+        default: return euler_phase_kernel<0>(dtype);
+    }
 }
 
 hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t lds, hipStream_t st)
@@ -214,16 +225,17 @@ hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t 
     const int t2 = a.tiles * a.tiles;
     const int nblk = (a.phase & 1) ? 2 * t2 : t2;
     void* args[] = {(void*)&a};
-    return hipLaunchKernel(phase_kernel(kind, dtype, a.tile), dim3(nblk), dim3(wg), args, lds, st);
+    return hipLaunchKernel(phase_kernel(kind, dtype, a.tile, a.scheme), dim3(nblk), dim3(wg), args, lds, st);
 }
 
 hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds)
 {
     hipError_t e = hipSuccess;
-    for (int tile : {0, 16, 32, 64})
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                    (int)lds);
+    for (int scheme = 0; scheme < (kind == 0 ? 1 : 4); ++scheme)
+        for (int tile : {0, 16, 32, 64})
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile, scheme),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return e;
 }
 
@@ -249,21 +261,36 @@ size_t euler_phase_lds(int dtype, int tile)
     return s * euler_lds_values(tile + 4, (tile + 1) * tile);
 }
 
+template <int V>
+static const void* euler_standard_v(int dtype)
+{
+    return dtype == 0 ? (const void*)euler_standard_kernel<double, V> : (const void*)euler_standard_kernel<float, V>;
+}
+
+static const void* euler_standard(int dtype, int scheme)
+{
+    switch (scheme) {
+        case 1: return euler_standard_v<1>(dtype);
+        case 2: return euler_standard_v<2>(dtype);
+        case 3: return euler_standard_v<3>(dtype);
+        default: return euler_standard_v<0>(dtype);
+    }
+}
+
 hipError_t set_euler_standard_lds_limit(int dtype, size_t lds)
 {
-    const void* f = dtype == 0 ? (const void*)euler_standard_kernel<double> : (const void*)euler_standard_kernel<float>;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipSuccess;
+    for (int scheme = 0; scheme < 4 && e == hipSuccess; ++scheme)
+        e = hipFuncSetAttribute(euler_standard(dtype, scheme), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return e;
 }
 
 hipError_t launch_euler_standard(int dtype, const void* in, void* out, const StdArgs& a, hipStream_t st)
 {
     dim3 grd(a.N / a.ts, a.N / a.ts);
     const size_t lds = euler_standard_lds(dtype, a.ts);
-    if (dtype == 0)
-        hipLaunchKernelGGL(euler_standard_kernel<double>, grd, dim3(256), lds, st, (const double*)in, (double*)out, a);
-    else
-        hipLaunchKernelGGL(euler_standard_kernel<float>, grd, dim3(256), lds, st, (const float*)in, (float*)out, a);
-    return hipGetLastError();
+    void* args[] = {(void*)&in, (void*)&out, (void*)&a};
+    return hipLaunchKernel(euler_standard(dtype, a.scheme), grd, dim3(256), args, lds, st);
 }
 
 hipError_t launch_plane_sums(int dtype, const void* x, int nvar, size_t NN, double* partials, int nparts,

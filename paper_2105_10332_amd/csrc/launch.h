@@ -43,6 +43,7 @@ struct PhaseArgs {
     double* partials;  // adjoint only: one pairing partial sum per workgroup
     int shift;         // adjoint only: 1 = the reversed sweep runs on the other tiling
     int kind;          // batch only: 0 heat, 1 Euler (single-problem launches pick the kernel by template)
+    int scheme;        // Euler scheme variant bits (scheme.h); picks the kernel instantiation, 0 for heat
     int N;        // cells per side
     int tile;     // b
     int h;        // b / (2n)
@@ -55,7 +56,8 @@ struct PhaseArgs {
 
 struct StdArgs {
     int N;
-    int ts;  // output tile edge of the fused Euler step
+    int ts;      // output tile edge of the fused Euler step
+    int scheme;  // Euler scheme variant bits (scheme.h)
     double p[5];
 };
 

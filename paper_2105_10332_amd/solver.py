@@ -12,14 +12,16 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import EULER, F32, F64, HEAT, Info, Problem, Tuning, check, lib
+from ._lib import EULER, F32, F64, HEAT, LIMITER_LITERAL, SPEED_ROE, Info, Problem, Tuning, check, lib
 
 _DT = {torch.float64: F64, torch.float32: F32}
 
 
 def make_problem(kind: int, n: int, dtype: torch.dtype, dt: float, length: float, alpha: float = 1.0,
-                 gamma: float = 1.4) -> Problem:
-    return Problem(kind, _DT[dtype], n, n, float(length), float(length), float(dt), float(alpha), float(gamma))
+                 gamma: float = 1.4, scheme: int = 0) -> Problem:
+    """scheme: Euler variant bits, LIMITER_LITERAL | SPEED_ROE (0 = minmod + Rusanov)."""
+    return Problem(kind, _DT[dtype], n, n, float(length), float(length), float(dt), float(alpha), float(gamma),
+                   int(scheme), 0)
 
 
 def swept_workspace_bytes(prob: Problem, tile: int = 0, wg: int = 0) -> int:
@@ -48,14 +50,14 @@ class SweptSolver:
     """
 
     def __init__(self, kind: int, state: torch.Tensor, dt: float, length: float = 1.0, alpha: float = 1.0,
-                 gamma: float = 1.4, tile: int = 0, wg: int = 0):
+                 gamma: float = 1.4, tile: int = 0, wg: int = 0, scheme: int = 0):
         n = state.shape[-1]
         expect = (n, n) if kind == HEAT else (4, n, n)
         if tuple(state.shape) != expect:
             raise ValueError(f"state shape {tuple(state.shape)} != {expect}")
         self.kind = kind
         self.state = state
-        self.prob = make_problem(kind, n, state.dtype, dt, length, alpha, gamma)
+        self.prob = make_problem(kind, n, state.dtype, dt, length, alpha, gamma, scheme)
         nbytes = swept_workspace_bytes(self.prob, tile, wg)
         self.work = torch.empty(nbytes, dtype=torch.uint8, device=state.device)
         self._ctx = ctypes.c_void_p(0)
@@ -217,4 +219,5 @@ def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 
     return out.value
 
 
-__all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT", "EULER", "_lib"]
+__all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT",
+           "EULER", "LIMITER_LITERAL", "SPEED_ROE", "_lib"]

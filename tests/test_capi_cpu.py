@@ -66,6 +66,9 @@ def test_workspace_size():
     (heat(64), 16, 100, "SWEPT_EINVAL"),                                           # wg not multiple of 64
     (euler(64), 16, 1024, "SWEPT_EINVAL"),                                         # Euler wg > 512
     (Problem(0, 0, 0, 0, 1.0, 1.0, 1e-5, 1.0, 1.4), 16, 0, "SWEPT_ESHAPE"),        # empty
+    (Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 4), 16, 0, "SWEPT_EINVAL"),  # unknown scheme bit
+    (Problem(0, 0, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4, 1), 16, 0, "SWEPT_EINVAL"),    # heat has no variants
+    (Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 0, 1), 16, 0, "SWEPT_EINVAL"),  # reserved != 0
 ])
 def test_validation_codes(prob, tile, wg, code):
     rc, _ = _ws(prob, tile, wg)
@@ -129,3 +132,7 @@ def test_batch_count_and_dtype_validation():
     assert L.swept_batch_workspace_bytes(probs, None, 0, ctypes.byref(out)) == CODES["SWEPT_EINVAL"]
     mixed = (Problem * 2)(heat(32, dtype=0), heat(32, dtype=1))
     assert L.swept_batch_workspace_bytes(mixed, None, 2, ctypes.byref(out)) == CODES["SWEPT_EINVAL"]
+    variant = (Problem * 2)(heat(32), Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 3))
+    assert L.swept_batch_workspace_bytes(variant, None, 2, ctypes.byref(out)) == CODES["SWEPT_ENOTSUP"]
+    for scheme in (1, 2, 3):  # the single-problem path takes every variant
+        assert _ws(Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, scheme), 16)[0] == 0

@@ -34,6 +34,27 @@ def test_swept_equals_standard_and_oracle(dtype, tile, N):
         assert err <= (1e-10 if dtype == np.float64 else 1e-5), err
 
 
+@pytest.mark.parametrize("scheme", [1, 2, 3])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("tile,N", [(8, 24), (16, 48), (32, 64)])
+def test_scheme_variants_swept_equals_standard_and_oracle(scheme, dtype, tile, N):
+    """The limiter-as-printed and Roe-speed variants: Swept == Standard bit for bit and
+    both match the oracle run with the same variant bits."""
+    Q0 = problems.shu_vortex(N)
+    dt = _dt(Q0, N)
+    Q0 = Q0.astype(dtype)
+    h = tile // 4
+    for steps in sorted({1, h + 1, 2 * h + 3}):
+        sw = euler_gpu(Q0, dt, steps, tile, "swept", scheme=scheme)
+        st = euler_gpu(Q0, dt, steps, tile, "standard", scheme=scheme)
+        assert np.array_equal(sw, st), (scheme, tile, N, steps)
+        ref = oracle.euler_run(Q0, dt, 10.0 / N, 10.0 / N, GAMMA, steps, scheme=scheme)
+        err = rel_err(sw, ref)
+        assert err <= (1e-10 if dtype == np.float64 else 1e-5), err
+        if dtype == np.float64 and steps > 1:
+            assert rel_err(ref, oracle.euler_run(Q0, dt, 10.0 / N, 10.0 / N, GAMMA, steps)) > 1e-12
+
+
 def test_poisoned_workspace_and_determinism():
     Q0 = problems.shu_vortex(64)
     dt = _dt(Q0, 64)
