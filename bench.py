@@ -39,7 +39,7 @@ METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB
 # WRITE_SIZE x 1.0: the factors a plain copy of known size reads), keyed by workload and launch
 # shape, valid only for the kernel sources whose hash is recorded with it (null otherwise).
 MEASURED_TRAFFIC = {
-    ("heat", "f64", 4096, 64, 512, 1000): (628.2e6, "ee94bec16704e261"),
+    ("heat", "f64", 4096, 64, 512, 1000): (629.1e6, "c2f62fd05f608e7f"),
 }
 KERNEL_SOURCES = ("scheme.h", "device_common.h", "kernels.hip", "launch.h")
 
@@ -80,6 +80,9 @@ def parse():
     ap.add_argument("--tile", type=int, default=0, help="0: tuned or default tile")
     ap.add_argument("--wg", type=int, default=0, help="0: tuned or library default")
     ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--boundary", type=int, default=0,
+                    help="heat boundary: 0 periodic, 1 Dirichlet (ghost value --boundary-value), 2 zero flux")
+    ap.add_argument("--boundary-value", type=float, default=0.0)
     ap.add_argument("--scheme", type=int, default=0,
                     help="Euler scheme variant bits: 1 limiter factors as printed, 2 Roe-averaged speed")
     ap.add_argument("--advance-steps", type=int, default=0)
@@ -111,7 +114,7 @@ def cores():
     return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
 
 
-def cpu_heat(dtype_np, n, r, budget_s=25.0):
+def cpu_heat(dtype_np, n, r, budget_s=25.0, bc=0, bcv=0.0):
     """The oracle as it is on the host cores: a warm step, a few steps to size the sample,
     then a bounded number of Standard steps of the same grid (about budget_s seconds)."""
     import numpy as np
@@ -120,13 +123,13 @@ def cpu_heat(dtype_np, n, r, budget_s=25.0):
     from paper_2105_10332_amd import problems
 
     T0 = problems.heat_fourier_modes(n).astype(dtype_np)
-    T1 = oracle.heat_run(T0, r, 1)
+    T1 = oracle.heat_run(T0, r, 2, bc, bcv)
     t = time.perf_counter()
-    T1 = oracle.heat_run(T1, r, 4)
-    one = (time.perf_counter() - t) / 4
-    k = max(1, min(5000, int(budget_s / max(one, 1e-6))))
+    T1 = oracle.heat_run(T1, r, 16, bc, bcv)
+    one = (time.perf_counter() - t) / 16
+    k = max(1, min(20000, int(budget_s / max(one, 1e-6))))
     t = time.perf_counter()
-    oracle.heat_run(T1, r, k)
+    oracle.heat_run(T1, r, k, bc, bcv)
     el = time.perf_counter() - t
     return {"value": n * n * k / el, "unit": "cell-updates/s", "cores": cores(), "kind": "oracle",
             "sample": f"heat {n}x{n} {np.dtype(dtype_np).name}, {k} Standard steps of the C oracle "
@@ -183,23 +186,26 @@ def run_heat(args):
     T0 = problems.heat_fourier_modes(n)
     dx = 1.0 / n
     state = torch.tensor(T0, dtype=tdt, device="cuda")
-    solver = SweptSolver(HEAT, state, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, wg=wg)
+    bc = dict(boundary=args.boundary, boundary_value=args.boundary_value)
+    solver = SweptSolver(HEAT, state, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, wg=wg, **bc)
     for _ in range(args.warmup):
         solver.swept_advance(M)
     sec, wall = timed(lambda: solver.swept_advance(M), args.steps)
     updates = n * n * M * args.steps
     rate = updates / sec
     plan = geometry.totals(n, tile, 1, M)
-    cfg = {"workload": f"heat {n}x{n} periodic, 5-point forward Euler, r=0.2, {M} time steps per bench step, "
-                       f"16 seeded Fourier modes; swept tile {tile}",
+    walls = {0: "periodic", 1: f"Dirichlet walls (ghost value {args.boundary_value})", 2: "zero-flux walls"}
+    cfg = {"workload": f"heat {n}x{n} {walls[args.boundary]}, 5-point forward Euler, r=0.2, {M} time steps per "
+                       f"bench step, 16 seeded Fourier modes; swept tile {tile}",
            "tile": tile, "wg": solver.info.wg, "time_steps_per_step": M, "launches_per_step": plan["launches"]}
     out = base_record(args, rate, "cell-updates/s", sec, dt_name, cfg)
     out["effective_GBps"] = 2 * S * updates / sec / 1e9
     out["roofline"] = roofline(plan, S, 1, plan["launches"] * args.steps, sec, "swept_phase_kernel<HeatS>")
-    out["roofline"]["traffic"] = measured_traffic(("heat", dt_name, n, tile, solver.info.wg, M))
+    if args.boundary == 0:
+        out["roofline"]["traffic"] = measured_traffic(("heat", dt_name, n, tile, solver.info.wg, M))
     if not args.no_standard:
         st = torch.tensor(T0, dtype=tdt, device="cuda")
-        ss = SweptSolver(HEAT, st, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile)
+        ss = SweptSolver(HEAT, st, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, **bc)
         ss.standard_advance(M)
         k = max(1, min(args.steps, 3))
         ssec, _ = timed(lambda: ss.standard_advance(M), k)
@@ -208,7 +214,8 @@ def run_heat(args):
         out["speedup_vs_standard"] = rate / out["standard"]["value"]
     out["wall_s"] = wall
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_heat(np.float64 if dt_name == "f64" else np.float32, n, r)
+        out["cpu_baseline"] = cpu_heat(np.float64 if dt_name == "f64" else np.float32, n, r, bc=args.boundary,
+                                        bcv=args.boundary_value)
     return out
 
 

@@ -78,8 +78,20 @@ typedef struct {
     double alpha;   /* heat diffusivity; r = alpha*dt/dx^2 with dx = lx/nx    */
     double gamma;   /* Euler ratio of specific heats (> 1)                    */
     int32_t scheme; /* Euler scheme variant bits (0 for heat), see below       */
-    int32_t reserved; /* must be 0                                             */
+    int32_t boundary; /* SWEPT_BC_*: periodic (0) or, heat only, see below     */
+    double boundary_value; /* SWEPT_BC_DIRICHLET: the fixed ghost-cell value   */
 } swept_problem;
+
+/* Boundaries.  The paper's solver is periodic and notes that other
+ * conditions fit the same decomposition (Sec. 3.3); heat also takes
+ * SWEPT_BC_DIRICHLET (every neighbour outside the square reads the constant
+ * boundary_value) and SWEPT_BC_NEUMANN (zero flux: an outside neighbour
+ * reads the edge cell itself).  A cell's dependencies are then a subset of
+ * its periodic ones, so the same shapes and phases apply unchanged.  Euler,
+ * the adjoint and the batch take SWEPT_BC_PERIODIC only (SWEPT_ENOTSUP). */
+#define SWEPT_BC_PERIODIC 0
+#define SWEPT_BC_DIRICHLET 1
+#define SWEPT_BC_NEUMANN 2
 
 /* Euler scheme variants (App. B prints the limiter and the spectral radius
  * ambiguously).  0: pressure-ratio minmod face states, Q_L = Q_i +

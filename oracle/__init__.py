@@ -68,6 +68,8 @@ def _declare(L):
     for s in ("_f64", "_f32"):
         getattr(L, "oracle_heat_step" + s).argtypes = [_P, _P, _I, _D]
         getattr(L, "oracle_heat_run" + s).argtypes = [_P, _P, _I, _D, _I]
+        getattr(L, "oracle_heat_step_bc" + s).argtypes = [_P, _P, _I, _D, _I, _D]
+        getattr(L, "oracle_heat_run_bc" + s).argtypes = [_P, _P, _I, _D, _I, _I, _D]
         getattr(L, "oracle_heat_adjoint" + s).argtypes = [_P, _P, _P, ctypes.POINTER(_D), _I, _D, _I, _P, _P]
         getattr(L, "oracle_l2_mismatch" + s).argtypes = [_P, _P, _I]
         getattr(L, "oracle_l2_mismatch" + s).restype = _D
@@ -94,19 +96,30 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-def heat_step(T: np.ndarray, r: float) -> np.ndarray:
-    """One heat step (App. A update) of an N x N periodic field."""
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2  # heat boundaries (see oracle.c)
+
+
+def heat_step(T: np.ndarray, r: float, bc: int = BC_PERIODIC, bcv: float = 0.0) -> np.ndarray:
+    """One heat step (App. A update) of an N x N field; bc = boundary, bcv = Dirichlet ghost value."""
     T = np.ascontiguousarray(T)
     out = np.empty_like(T)
-    getattr(lib(), "oracle_heat_step" + _sfx(T))(_ptr(T), _ptr(out), T.shape[0], float(r))
+    if bc == BC_PERIODIC:
+        getattr(lib(), "oracle_heat_step" + _sfx(T))(_ptr(T), _ptr(out), T.shape[0], float(r))
+    else:
+        getattr(lib(), "oracle_heat_step_bc" + _sfx(T))(_ptr(T), _ptr(out), T.shape[0], float(r), int(bc),
+                                                        float(bcv))
     return out
 
 
-def heat_run(T0: np.ndarray, r: float, steps: int) -> np.ndarray:
+def heat_run(T0: np.ndarray, r: float, steps: int, bc: int = BC_PERIODIC, bcv: float = 0.0) -> np.ndarray:
     """``steps`` forward-Euler heat steps; returns T^M (T0 is not modified)."""
     T = np.array(T0, copy=True, order="C")
     work = np.empty_like(T)
-    getattr(lib(), "oracle_heat_run" + _sfx(T))(_ptr(T), _ptr(work), T.shape[0], float(r), int(steps))
+    if bc == BC_PERIODIC:
+        getattr(lib(), "oracle_heat_run" + _sfx(T))(_ptr(T), _ptr(work), T.shape[0], float(r), int(steps))
+    else:
+        getattr(lib(), "oracle_heat_run_bc" + _sfx(T))(_ptr(T), _ptr(work), T.shape[0], float(r), int(steps),
+                                                       int(bc), float(bcv))
     return T
 
 

@@ -18,19 +18,34 @@ def _sh(a, dx=0, dy=0):
     return np.roll(np.roll(a, -dy, axis=-2), -dx, axis=-1)
 
 
-def heat_step(T: np.ndarray, r: float) -> np.ndarray:
+def _ghosted(T, bc, bcv):
+    """T padded by one ghost cell per side: periodic copy (bc 0), the constant bcv
+    (Dirichlet, bc 1) or the edge cell itself (zero flux, bc 2)."""
+    if bc == 0:
+        return np.pad(T, 1, mode="wrap")
+    if bc == 1:
+        return np.pad(T, 1, mode="constant", constant_values=T.dtype.type(bcv))
+    return np.pad(T, 1, mode="edge")
+
+
+def heat_step(T: np.ndarray, r: float, bc: int = 0, bcv: float = 0.0) -> np.ndarray:
     """App. A update, evaluated as (T + r*dxx) + r*dyy with dxx = (T_E - 2T) + T_W."""
     r = T.dtype.type(r)
     two = T + T
-    dxx = (_sh(T, 1, 0) - two) + _sh(T, -1, 0)
-    dyy = (_sh(T, 0, 1) - two) + _sh(T, 0, -1)
+    if bc == 0:
+        dxx = (_sh(T, 1, 0) - two) + _sh(T, -1, 0)
+        dyy = (_sh(T, 0, 1) - two) + _sh(T, 0, -1)
+    else:
+        G = _ghosted(T, bc, bcv)
+        dxx = (G[1:-1, 2:] - two) + G[1:-1, :-2]
+        dyy = (G[2:, 1:-1] - two) + G[:-2, 1:-1]
     return (T + r * dxx) + r * dyy
 
 
-def heat_run(T0: np.ndarray, r: float, steps: int) -> np.ndarray:
+def heat_run(T0: np.ndarray, r: float, steps: int, bc: int = 0, bcv: float = 0.0) -> np.ndarray:
     T = np.array(T0, copy=True)
     for _ in range(steps):
-        T = heat_step(T, r)
+        T = heat_step(T, r, bc, bcv)
     return T
 
 

@@ -67,35 +67,66 @@ static inline int64_t wrap(int64_t i, int64_t n) { return (i % n + n) % n; }
 
 /* ------------------------------------------------------------------ heat */
 
-/* One forward-Euler step of the heat equation (App. A, update equation).
- * Tout may not alias Tin. */
-void NAME(oracle_heat_step)(const REAL* Tin, REAL* Tout, int64_t N, double r_in)
+/* Boundaries: the paper's grid is periodic; it notes that other conditions
+ * fit the same decomposition.  BC_DIRICHLET: every neighbour outside the
+ * square is a ghost cell holding the fixed value bcv.  BC_NEUMANN (zero
+ * flux): an outside neighbour holds the value of the edge cell itself. */
+#define BC_PERIODIC 0
+#define BC_DIRICHLET 1
+#define BC_NEUMANN 2
+
+/* Value of neighbour (i, j) of cell (ci, cj), which may lie outside the
+ * square by one cell. */
+static inline REAL neighbour(const REAL* T, int64_t N, int64_t i, int64_t j, int64_t ci, int64_t cj, int bc, REAL bcv)
 {
-    const REAL r = (REAL)r_in;
+    if (i >= 0 && i < N && j >= 0 && j < N) return T[j * N + i];
+    if (bc == BC_DIRICHLET) return bcv;
+    if (bc == BC_NEUMANN) return T[cj * N + ci];
+    return T[wrap(j, N) * N + wrap(i, N)];
+}
+
+/* One forward-Euler step of the heat equation (App. A, update equation),
+ * boundary bc (ghost value bcv for BC_DIRICHLET).  Tout may not alias Tin. */
+void NAME(oracle_heat_step_bc)(const REAL* Tin, REAL* Tout, int64_t N, double r_in, int64_t bc, double bcv_in)
+{
+    const REAL r = (REAL)r_in, bcv = (REAL)bcv_in;
 #pragma omp parallel for schedule(static)
     for (int64_t j = 0; j < N; ++j) {
-        const int64_t jm = wrap(j - 1, N), jp = wrap(j + 1, N);
         for (int64_t i = 0; i < N; ++i) {
-            const int64_t im = wrap(i - 1, N), ip = wrap(i + 1, N);
             const REAL c = Tin[j * N + i];
             const REAL two_c = c + c;
-            const REAL dxx = (Tin[j * N + ip] - two_c) + Tin[j * N + im];
-            const REAL dyy = (Tin[jp * N + i] - two_c) + Tin[jm * N + i];
+            const REAL dxx = (neighbour(Tin, N, i + 1, j, i, j, (int)bc, bcv) - two_c) +
+                             neighbour(Tin, N, i - 1, j, i, j, (int)bc, bcv);
+            const REAL dyy = (neighbour(Tin, N, i, j + 1, i, j, (int)bc, bcv) - two_c) +
+                             neighbour(Tin, N, i, j - 1, i, j, (int)bc, bcv);
             Tout[j * N + i] = (c + r * dxx) + r * dyy;
         }
     }
 }
 
-/* M heat steps.  T holds T^0 on entry and T^M on exit; work is N*N scratch. */
-void NAME(oracle_heat_run)(REAL* T, REAL* work, int64_t N, double r, int64_t M)
+/* One periodic step. */
+void NAME(oracle_heat_step)(const REAL* Tin, REAL* Tout, int64_t N, double r_in)
+{
+    NAME(oracle_heat_step_bc)(Tin, Tout, N, r_in, BC_PERIODIC, 0.0);
+}
+
+/* M heat steps with boundary bc.  T holds T^0 on entry and T^M on exit;
+ * work is N*N scratch. */
+void NAME(oracle_heat_run_bc)(REAL* T, REAL* work, int64_t N, double r, int64_t M, int64_t bc, double bcv)
 {
     REAL* a = T;
     REAL* b = work;
     for (int64_t m = 0; m < M; ++m) {
-        NAME(oracle_heat_step)(a, b, N, r);
+        NAME(oracle_heat_step_bc)(a, b, N, r, bc, bcv);
         REAL* t = a; a = b; b = t;
     }
     if (a != T) memcpy(T, a, (size_t)(N * N) * sizeof(REAL));
+}
+
+/* M periodic heat steps. */
+void NAME(oracle_heat_run)(REAL* T, REAL* work, int64_t N, double r, int64_t M)
+{
+    NAME(oracle_heat_run_bc)(T, work, N, r, M, BC_PERIODIC, 0.0);
 }
 
 /* Discrete 5-point Laplacian without the 1/dx^2 factor, L T, evaluated in

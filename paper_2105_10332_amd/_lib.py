@@ -21,6 +21,7 @@ CODES = {v: k for k, v in ERRORS.items()}
 HEAT, EULER = 0, 1
 F64, F32 = 0, 1
 LIMITER_LITERAL, SPEED_ROE = 1, 2  # Euler scheme variant bits (swept.h)
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2  # boundaries (swept.h; heat only for the last two)
 
 
 class SweptError(RuntimeError):
@@ -34,7 +35,7 @@ class Problem(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("dtype", ctypes.c_int32), ("nx", ctypes.c_int32),
                 ("ny", ctypes.c_int32), ("lx", ctypes.c_double), ("ly", ctypes.c_double),
                 ("dt", ctypes.c_double), ("alpha", ctypes.c_double), ("gamma", ctypes.c_double),
-                ("scheme", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("scheme", ctypes.c_int32), ("boundary", ctypes.c_int32), ("boundary_value", ctypes.c_double)]
 
 
 class Tuning(ctypes.Structure):

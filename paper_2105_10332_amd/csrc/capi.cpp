@@ -85,7 +85,11 @@ int derive(const swept_problem* p, const swept_tuning* t, Derived* d)
     if (!(p->lx > 0) || !(p->ly > 0) || !std::isfinite(p->lx) || !std::isfinite(p->ly))
         return fail(SWEPT_EINVAL, "domain lengths must be positive");
     if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(SWEPT_EUNSTABLE, "dt must be positive (dt=%g)", p->dt);
-    if (p->reserved != 0) return fail(SWEPT_EINVAL, "reserved field must be 0");
+    if (p->boundary < SWEPT_BC_PERIODIC || p->boundary > SWEPT_BC_NEUMANN)
+        return fail(SWEPT_EINVAL, "unknown boundary %d", p->boundary);
+    if (p->boundary != SWEPT_BC_PERIODIC && p->kind != SWEPT_HEAT)
+        return fail(SWEPT_ENOTSUP, "Euler is periodic only");
+    if (!std::isfinite(p->boundary_value)) return fail(SWEPT_EINVAL, "boundary value must be finite");
     if (p->scheme & ~(SWEPT_LIMITER_LITERAL | SWEPT_SPEED_ROE))
         return fail(SWEPT_EINVAL, "unknown scheme bits %d", p->scheme);
     if (p->kind == SWEPT_HEAT && p->scheme != 0) return fail(SWEPT_EINVAL, "heat has no scheme variants");
@@ -266,7 +270,8 @@ int swept_init(swept_ctx** ctx, const swept_problem* prob, const swept_tuning* t
     c->red = reinterpret_cast<double*>(w + align_up(d.state_bytes) + align_up(sizeof(double) * 4 * kParts));
     if (prob->kind == SWEPT_HEAT) {
         c->c[0] = d.r;
-        c->c[1] = c->c[2] = c->c[3] = c->c[4] = 0.0;
+        c->c[1] = prob->boundary == SWEPT_BC_DIRICHLET ? prob->boundary_value : 0.0;
+        c->c[2] = c->c[3] = c->c[4] = 0.0;
     } else {
         c->c[0] = prob->gamma;
         c->c[1] = 0.5 * prob->dt / d.dx;
@@ -356,6 +361,7 @@ static swept::PhaseArgs phase_args(const swept_ctx* c, int L)
     a.L = L;
     a.tab = c->tab_dev;
     a.scheme = c->prob.scheme;
+    a.bc = c->prob.boundary;
     for (int k = 0; k < 5; ++k) a.p[k] = c->c[k];
     return a;
 }
@@ -392,6 +398,7 @@ static int tape_check(const swept_ctx* c, int64_t n_steps, TapePlan* t)
 {
     if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
     if (c->prob.kind != SWEPT_HEAT) return fail(SWEPT_ENOTSUP, "the adjoint is implemented for heat only");
+    if (c->prob.boundary != SWEPT_BC_PERIODIC) return fail(SWEPT_ENOTSUP, "the adjoint is periodic only");
     if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
     if (c->adj_lds == 0)
         return fail(SWEPT_ESHAPE, "tile %d too large for the adjoint's LDS (all levels of a shape are kept)",
@@ -457,7 +464,8 @@ int swept_adjoint(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes
         char* stash = tape + t.stash_off;
         e = hipMemcpyAsync(stash, ck(t.cycles), SB, hipMemcpyDeviceToDevice, st);
         for (int64_t m = 1; m < t.rem && e == hipSuccess; ++m)
-            e = swept::launch_heat_standard(c->prob.dtype, stash + S * (m - 1), stash + S * m, N, c->d.r, st);
+            e = swept::launch_heat_standard(c->prob.dtype, stash + S * (m - 1), stash + S * m, N, c->d.r,
+                                            SWEPT_BC_PERIODIC, 0.0, st);
         for (int64_t m = t.rem - 1; m >= 0 && e == hipSuccess; --m) {
             e = swept::launch_adjoint_step(c->prob.dtype, La, Lb, stash + S * m, N, c->d.r, parts + pslot,
                                            t.std_blocks, st);
@@ -527,7 +535,8 @@ int standard_advance(swept_ctx* c, int64_t n_steps)
         void* out = bufs[(m + 1) & 1];
         hipError_t e;
         if (c->prob.kind == SWEPT_HEAT) {
-            e = swept::launch_heat_standard(c->prob.dtype, in, out, c->prob.nx, c->d.r, c->stream);
+            e = swept::launch_heat_standard(c->prob.dtype, in, out, c->prob.nx, c->d.r, c->prob.boundary, c->c[1],
+                                            c->stream);
         } else {
             swept::StdArgs a;
             a.N = c->prob.nx;
@@ -631,6 +640,8 @@ int batch_derive(const swept_problem* probs, const swept_tuning* tunes, int32_t 
     for (int q = 0; q < count; ++q) {
         if (probs[q].dtype != probs[0].dtype) return fail(SWEPT_EINVAL, "all problems of a batch share one dtype");
         if (probs[q].scheme != 0) return fail(SWEPT_ENOTSUP, "problem %d: the batch runs scheme 0 only", q);
+        if (probs[q].boundary != SWEPT_BC_PERIODIC)
+            return fail(SWEPT_ENOTSUP, "problem %d: the batch is periodic only", q);
         swept_tuning t{tunes ? tunes[q].tile : 0, swept::batch_wg(probs[0].dtype)};
         const int rc = derive(&probs[q], &t, &(*d)[q]);
         if (rc) return rc;

@@ -24,14 +24,17 @@ __device__ __forceinline__ int wrapi(int g, int N)
     return g;
 }
 
-struct HeatS {
-    static constexpr int NVAR = 1, R = 1, TWO_STAGE = 0, MAXWG = 1024, SCHEME = 0;
+// Heat with boundary BC (0 periodic, 1 Dirichlet ghost value, 2 zero flux)
+template <int BC>
+struct HeatSV {
+    static constexpr int NVAR = 1, R = 1, TWO_STAGE = 0, MAXWG = 1024, SCHEME = 0, BOUNDARY = BC;
 };
+using HeatS = HeatSV<0>;
 // Euler with scheme variant V (limiter and spectral-radius bits, scheme.h);
 // register-heavy per-cell update: at most 512 threads (FP32) or 256 (FP64)
 template <int V>
 struct EulerSV {
-    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 512, SCHEME = V;
+    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 512, SCHEME = V, BOUNDARY = 0;
 };
 using EulerS = EulerSV<0>;
 
@@ -313,11 +316,17 @@ __host__ __device__ inline size_t euler_lds_values(int W, int FS) { return (size
 // LDS row pitch).  Cells outside F(l+2) (half-widths hx2, hy2) also go to
 // the level's global buffer.  WRAP = false when the window does not cross
 // the periodic boundary, so global indices need no wrap.
-template <typename T, bool WRAP>
+//
+// BC != 0 (only with WRAP: a window that stays inside the square never
+// reaches its edge) replaces every neighbour outside the square by a ghost
+// value: the constant bcv (Dirichlet, BC = 1) or the edge cell itself (zero
+// flux, BC = 2).  The window's wrapped copy of the far side is then unused.
+template <typename T, bool WRAP, int BC = 0>
 __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ gout,
                                            int W, int C, const LevelEntry& e, int hx2, int hy2, int ox, int oy,
-                                           int N, T r)
+                                           int N, T r, T bcv = T(0))
 {
+    static_assert(BC == 0 || WRAP, "boundaries are met only by windows that cross the edge");
     const int pw = e.pw, nthr = blockDim.x;
     const int NN = N * N;
     const int ylo2 = C - hy2, yhi2 = C + hy2;  // rows inside F(l+2)
@@ -329,15 +338,27 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
         const bool xk0 = (x - C >= -hx2) && (x - C < hx2);
         const bool xk1 = (x + 1 - C >= -hx2) && (x + 1 - C < hx2);
         const int gx0 = WRAP ? wrapi(ox + x, N) : ox + x, gx1 = WRAP ? wrapi(ox + x + 1, N) : ox + x + 1;
-        int grow = (WRAP ? wrapi(oy + ys, N) : oy + ys) * N;
+        int gy = WRAP ? wrapi(oy + ys, N) : oy + ys;
+        int grow = gy * N;
         int li = ys * W + x;
         T up0 = prev[li - W], up1 = prev[li - W + 1];
         T c0 = prev[li], c1 = prev[li + 1];
         for (int y = ys; y < ye; ++y) {
             const T dn0 = prev[li + W], dn1 = prev[li + W + 1];
             const T lft = prev[li - 1], rgt = prev[li + 2];
-            const T v0 = heat_update<T>(c0, c1, lft, dn0, up0, r);
-            const T v1 = heat_update<T>(c1, rgt, c0, dn1, up1, r);
+            T v0, v1;
+            if constexpr (BC != 0) {
+                // the pair straddles the x edge iff gx0 == N-1 (then gx1 == 0)
+                const bool xl = gx0 == 0, xm = gx0 == N - 1, xr = gx1 == N - 1;
+                const bool yt = gy == 0, yb = gy == N - 1;
+                const T g0 = BC == 1 ? bcv : c0, g1 = BC == 1 ? bcv : c1;
+                v0 = heat_update<T>(c0, xm ? g0 : c1, xl ? g0 : lft, yb ? g0 : dn0, yt ? g0 : up0, r);
+                v1 = heat_update<T>(c1, xr ? g1 : rgt, xm ? g1 : c0, yb ? g1 : dn1, yt ? g1 : up1, r);
+                gy = gy + 1 == N ? 0 : gy + 1;
+            } else {
+                v0 = heat_update<T>(c0, c1, lft, dn0, up0, r);
+                v1 = heat_update<T>(c1, rgt, c0, dn1, up1, r);
+            }
             cur[li] = v0;
             cur[li + 1] = v1;
             const bool yk = (y >= ylo2) && (y < yhi2);
@@ -368,6 +389,9 @@ constexpr int max_wg()
 template <class S, typename T, int B = 0>
 __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsigned char* smem_raw)
 {
+    // heat: windows that cross the domain edge first (-2.7% FP64, -3.6% FP32 on the
+    // 4096^2 advance); Euler keeps the row-major order (edge-first measured +1%)
+    constexpr bool ORDER_EDGE_FIRST = S::NVAR == 1;
     T* lds = reinterpret_cast<T*>(smem_raw);
     constexpr int NVAR = S::NVAR, R = S::R;
     const int b = B > 0 ? B : a.tile, h = B > 0 ? B / (2 * R) : a.h, N = a.N, L = a.L;
@@ -388,7 +412,30 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         wx = k ? w - 1 : w;
         wy = k ? w : w - 1;
     }
-    const int jx = inst % tiles, jy = inst / tiles;
+    int jx, jy;
+    if constexpr (ORDER_EDGE_FIRST) {
+        // windows that cross the domain edge take the slower path (periodic
+        // wrap or ghost values): give them the lowest workgroup indices so
+        // they start first.  The wrapping row and column are jy = ey and
+        // jx = ex (centres at 0 for odd w, at N - b/2 for even w); then that
+        // column without its corner; then the rest.
+        const int ex = (wx & 1) ? 0 : tiles - 1, ey = (wy & 1) ? 0 : tiles - 1, m = tiles - 1;
+        if (inst < tiles) {
+            jx = inst;
+            jy = ey;
+        } else if (inst < 2 * tiles - 1) {
+            const int k = inst - tiles;
+            jx = ex;
+            jy = k < ey ? k : k + 1;
+        } else {
+            const int k = inst - (2 * tiles - 1), ix = k % m, iy = k / m;
+            jx = ix < ex ? ix : ix + 1;
+            jy = iy < ey ? iy : iy + 1;
+        }
+    } else {
+        jx = inst % tiles;
+        jy = inst / tiles;
+    }
     const int wmax = wx > wy ? wx : wy, wmin = wx < wy ? wx : wy;
     const int lo = max(1, (wmax - 1) * h + 1);
     const int hi = min(L, (wmin + 1) * h - 1);
@@ -428,7 +475,8 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         T* gout = (lvl & 1) ? g1 : g0;
         if constexpr (NVAR == 1) {
             if (wraps)
-                heat_level<T, true>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
+                heat_level<T, true, S::BOUNDARY>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0],
+                                                 (T)a.p[1]);
             else
                 heat_level<T, false>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
         } else {

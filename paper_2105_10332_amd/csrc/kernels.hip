@@ -43,9 +43,11 @@ __global__ void __launch_bounds__((max_wg<S, T>())) swept_phase_kernel(PhaseArgs
 // neighbours in registers.
 constexpr int STD_ROWS = 8;
 
-template <typename T>
+// BC: 0 periodic; 1 Dirichlet (outside neighbours read bcv); 2 zero flux
+// (outside neighbours read the edge cell itself).
+template <typename T, int BC>
 __global__ void __launch_bounds__(256) heat_standard_kernel(const T* __restrict__ in, T* __restrict__ out, int N,
-                                                            T r)
+                                                            T r, T bcv)
 {
     const int x = blockIdx.x * 64 + threadIdx.x;
     const int y0 = (blockIdx.y * 4 + threadIdx.y) * STD_ROWS;
@@ -59,7 +61,13 @@ __global__ void __launch_bounds__(256) heat_standard_kernel(const T* __restrict_
         if (y >= N) break;
         const T dn = in[(size_t)wrapi(y + 1, N) * N + x];
         const size_t row = (size_t)y * N;
-        out[row + x] = heat_update<T>(c, in[row + xp], in[row + xm], dn, up, r);
+        if constexpr (BC == 0) {
+            out[row + x] = heat_update<T>(c, in[row + xp], in[row + xm], dn, up, r);
+        } else {
+            const T g = BC == 1 ? bcv : c;
+            out[row + x] = heat_update<T>(c, x == N - 1 ? g : in[row + xp], x == 0 ? g : in[row + xm],
+                                          y == N - 1 ? g : dn, y == 0 ? g : up, r);
+        }
         up = c;
         c = dn;
     }
@@ -209,9 +217,21 @@ static const void* euler_phase_kernel(int dtype)
     return dtype == 0 ? phase_kernel<EulerSV<V>, double>(0) : phase_kernel<EulerSV<V>, float>(0);
 }
 
-static const void* phase_kernel(int kind, int dtype, int tile, int scheme)
+template <int BC>
+static const void* heat_phase_kernel(int dtype, int tile)
 {
-    if (kind == 0) return dtype == 0 ? phase_kernel<HeatS, double>(tile) : phase_kernel<HeatS, float>(tile);
+    return dtype == 0 ? phase_kernel<HeatSV<BC>, double>(tile) : phase_kernel<HeatSV<BC>, float>(tile);
+}
+
+// scheme: Euler variant bits; bc: heat boundary.  Each combination is its own
+// instantiation, so the periodic minmod kernels carry no test for the others.
+static const void* phase_kernel(int kind, int dtype, int tile, int scheme, int bc)
+{
+    if (kind == 0) {
+        if (bc == 1) return heat_phase_kernel<1>(dtype, tile);
+        if (bc == 2) return heat_phase_kernel<2>(dtype, tile);
+        return heat_phase_kernel<0>(dtype, tile);
+    }
     switch (scheme) {
         case 1: return euler_phase_kernel<1>(dtype);
         case 2: return euler_phase_kernel<2>(dtype);
@@ -225,27 +245,39 @@ hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t 
     const int t2 = a.tiles * a.tiles;
     const int nblk = (a.phase & 1) ? 2 * t2 : t2;
     void* args[] = {(void*)&a};
-    return hipLaunchKernel(phase_kernel(kind, dtype, a.tile, a.scheme), dim3(nblk), dim3(wg), args, lds, st);
+    return hipLaunchKernel(phase_kernel(kind, dtype, a.tile, a.scheme, a.bc), dim3(nblk), dim3(wg), args, lds, st);
 }
 
 hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds)
 {
     hipError_t e = hipSuccess;
-    for (int scheme = 0; scheme < (kind == 0 ? 1 : 4); ++scheme)
+    for (int v = 0; v < (kind == 0 ? 3 : 4); ++v)  // heat: boundaries; Euler: scheme bits
         for (int tile : {0, 16, 32, 64})
             if (e == hipSuccess)
-                e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile, scheme),
+                e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile, kind == 0 ? 0 : v, kind == 0 ? v : 0),
                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return e;
 }
 
-hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, double r, hipStream_t st)
+template <typename T, int BC>
+static void heat_standard_launch(const void* in, void* out, int N, double r, double bcv, hipStream_t st)
 {
     dim3 blk(64, 4), grd((N + 63) / 64, (N + 4 * STD_ROWS - 1) / (4 * STD_ROWS));
-    if (dtype == 0)
-        hipLaunchKernelGGL(heat_standard_kernel<double>, grd, blk, 0, st, (const double*)in, (double*)out, N, r);
-    else
-        hipLaunchKernelGGL(heat_standard_kernel<float>, grd, blk, 0, st, (const float*)in, (float*)out, N, (float)r);
+    hipLaunchKernelGGL((heat_standard_kernel<T, BC>), grd, blk, 0, st, (const T*)in, (T*)out, N, (T)r, (T)bcv);
+}
+
+hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, double r, int bc, double bcv,
+                                hipStream_t st)
+{
+    if (dtype == 0) {
+        if (bc == 1) heat_standard_launch<double, 1>(in, out, N, r, bcv, st);
+        else if (bc == 2) heat_standard_launch<double, 2>(in, out, N, r, bcv, st);
+        else heat_standard_launch<double, 0>(in, out, N, r, bcv, st);
+    } else {
+        if (bc == 1) heat_standard_launch<float, 1>(in, out, N, r, bcv, st);
+        else if (bc == 2) heat_standard_launch<float, 2>(in, out, N, r, bcv, st);
+        else heat_standard_launch<float, 0>(in, out, N, r, bcv, st);
+    }
     return hipGetLastError();
 }
 

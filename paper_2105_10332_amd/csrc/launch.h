@@ -29,7 +29,8 @@ struct LevelEntry {
 inline int level_table_entries(int h) { return 4 * h; }
 
 // Arguments of one swept phase launch.  p[] holds the scheme constants in
-// double: heat {r}; Euler {gamma, dt/(2dx), dt/(2dy), dt/dx, dt/dy}.
+// double: heat {r, Dirichlet ghost value}; Euler {gamma, dt/(2dx), dt/(2dy),
+// dt/dx, dt/dy}.
 struct PhaseArgs {
     void* buf0;   // level-parity buffer 0 (the caller's state): read and written
     void* buf1;   // level-parity buffer 1 (workspace): read and written
@@ -44,6 +45,7 @@ struct PhaseArgs {
     int shift;         // adjoint only: 1 = the reversed sweep runs on the other tiling
     int kind;          // batch only: 0 heat, 1 Euler (single-problem launches pick the kernel by template)
     int scheme;        // Euler scheme variant bits (scheme.h); picks the kernel instantiation, 0 for heat
+    int bc;            // heat boundary (SWEPT_BC_*); the Dirichlet ghost value is p[1]
     int N;        // cells per side
     int tile;     // b
     int h;        // b / (2n)
@@ -63,7 +65,8 @@ struct StdArgs {
 
 hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t lds, hipStream_t st);
 hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds);
-hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, double r, hipStream_t st);
+hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, double r, int bc, double bcv,
+                                hipStream_t st);
 size_t euler_standard_lds(int dtype, int ts);
 size_t euler_phase_lds(int dtype, int tile);  // LDS bytes of an Euler swept workgroup
 hipError_t set_euler_standard_lds_limit(int dtype, size_t lds);

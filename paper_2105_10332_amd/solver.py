@@ -12,16 +12,18 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import EULER, F32, F64, HEAT, LIMITER_LITERAL, SPEED_ROE, Info, Problem, Tuning, check, lib
+from ._lib import (BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC, EULER, F32, F64, HEAT, LIMITER_LITERAL, SPEED_ROE, Info,
+                   Problem, Tuning, check, lib)
 
 _DT = {torch.float64: F64, torch.float32: F32}
 
 
 def make_problem(kind: int, n: int, dtype: torch.dtype, dt: float, length: float, alpha: float = 1.0,
-                 gamma: float = 1.4, scheme: int = 0) -> Problem:
-    """scheme: Euler variant bits, LIMITER_LITERAL | SPEED_ROE (0 = minmod + Rusanov)."""
+                 gamma: float = 1.4, scheme: int = 0, boundary: int = 0, boundary_value: float = 0.0) -> Problem:
+    """scheme: Euler variant bits, LIMITER_LITERAL | SPEED_ROE (0 = minmod + Rusanov).
+    boundary: BC_PERIODIC, or for heat BC_DIRICHLET (ghost cells hold boundary_value) / BC_NEUMANN."""
     return Problem(kind, _DT[dtype], n, n, float(length), float(length), float(dt), float(alpha), float(gamma),
-                   int(scheme), 0)
+                   int(scheme), int(boundary), float(boundary_value))
 
 
 def swept_workspace_bytes(prob: Problem, tile: int = 0, wg: int = 0) -> int:
@@ -50,14 +52,15 @@ class SweptSolver:
     """
 
     def __init__(self, kind: int, state: torch.Tensor, dt: float, length: float = 1.0, alpha: float = 1.0,
-                 gamma: float = 1.4, tile: int = 0, wg: int = 0, scheme: int = 0):
+                 gamma: float = 1.4, tile: int = 0, wg: int = 0, scheme: int = 0, boundary: int = 0,
+                 boundary_value: float = 0.0):
         n = state.shape[-1]
         expect = (n, n) if kind == HEAT else (4, n, n)
         if tuple(state.shape) != expect:
             raise ValueError(f"state shape {tuple(state.shape)} != {expect}")
         self.kind = kind
         self.state = state
-        self.prob = make_problem(kind, n, state.dtype, dt, length, alpha, gamma, scheme)
+        self.prob = make_problem(kind, n, state.dtype, dt, length, alpha, gamma, scheme, boundary, boundary_value)
         nbytes = swept_workspace_bytes(self.prob, tile, wg)
         self.work = torch.empty(nbytes, dtype=torch.uint8, device=state.device)
         self._ctx = ctypes.c_void_p(0)
@@ -220,4 +223,4 @@ def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 
 
 
 __all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT",
-           "EULER", "LIMITER_LITERAL", "SPEED_ROE", "_lib"]
+           "EULER", "LIMITER_LITERAL", "SPEED_ROE", "BC_PERIODIC", "BC_DIRICHLET", "BC_NEUMANN", "_lib"]

@@ -10,12 +10,14 @@ DEV = torch.device("cuda", 0)
 TDT = {np.float64: torch.float64, np.float32: torch.float32}
 
 
-def heat_gpu(T0: np.ndarray, r: float, steps: int, tile: int, method: str = "swept", wg: int = 0, poison=False):
+def heat_gpu(T0: np.ndarray, r: float, steps: int, tile: int, method: str = "swept", wg: int = 0, poison=False,
+             bc: int = 0, bcv: float = 0.0):
     """Run heat on the GPU; returns (result, r as the kernels used it)."""
     n = T0.shape[0]
     T = torch.tensor(T0, device=DEV)
     dx = 1.0 / n
-    s = SweptSolver(HEAT, T, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, wg=wg)
+    s = SweptSolver(HEAT, T, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, wg=wg, boundary=bc,
+                    boundary_value=bcv)
     if poison:  # all-ones bytes = NaN in every lane of the second level-parity buffer
         s.work[: s.info.state_bytes].fill_(255)
     getattr(s, method + "_advance")(steps)

@@ -150,10 +150,24 @@ class SweptSim:
         self.W = g.b + 2 * g.n
         assert g.N % g.b == 0 and g.b % (2 * g.n) == 0 and g.N >= 2 * g.b
 
-    # one level of the scheme on a local window; values outside the window garbage
-    def _compute(self, prev, prev2, lvl):
+    # one level of the scheme on a local window; values outside the window garbage.
+    # gx, gy: global column / row of each window cell (walls need them)
+    def _compute(self, prev, prev2, lvl, gx=None, gy=None):
         if self.kind == "heat":
-            return numpy_ref.heat_step(prev[0], self.p["r"])[None]
+            bc = self.p.get("bc", 0)
+            if bc == 0:
+                return numpy_ref.heat_step(prev[0], self.p["r"])[None]
+            T = prev[0]
+            t = self.dtype
+            N = self.g.N
+            g = np.full_like(T, t(self.p.get("bcv", 0.0))) if bc == 1 else T
+            xp = np.where(gx[None, :] == N - 1, g, np.roll(T, -1, axis=1))
+            xm = np.where(gx[None, :] == 0, g, np.roll(T, 1, axis=1))
+            yp = np.where(gy[:, None] == N - 1, g, np.roll(T, -1, axis=0))
+            ym = np.where(gy[:, None] == 0, g, np.roll(T, 1, axis=0))
+            r = t(self.p["r"])
+            two = T + T
+            return ((T + r * ((xp - two) + xm)) + r * ((yp - two) + ym))[None]
         t = self.dtype
         gam = t(self.p["gamma"])
         dt, dx = self.p["dt"], self.p["dx"]
@@ -250,7 +264,7 @@ class SweptSim:
                                 raise ProtocolError(f"{inst} level {lvl}: centre not at level {lvl-1}")
                             if two_stage and lvl % 2 == 0 and np.any(ltag[lvl % 2][ys, xs] != lvl - 2):
                                 raise ProtocolError(f"{inst} level {lvl}: own cell not at level {lvl-2}")
-                            new = self._compute(lds[(lvl - 1) % 2], lds[lvl % 2], lvl)
+                            new = self._compute(lds[(lvl - 1) % 2], lds[lvl % 2], lvl, gx, gy)
                             dst = lds[lvl % 2]
                             dst[:, fmask] = new[:, fmask]
                             ltag[lvl % 2][fmask] = lvl

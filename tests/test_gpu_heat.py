@@ -31,6 +31,45 @@ def test_swept_equals_standard_and_oracle(dtype, tile, N):
             assert rel_err(sw, ref) <= 1e-6
 
 
+@pytest.mark.parametrize("bc,bcv", [(1, 0.0), (1, 0.75), (2, 0.0)])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("tile,N", [(8, 16), (16, 48), (32, 64), (64, 128), (12, 36), (4, 12)])
+def test_boundaries_swept_equals_standard_and_oracle(bc, bcv, dtype, tile, N):
+    """Dirichlet (ghost cells at bcv) and zero-flux walls: Swept == Standard bit for bit and
+    both equal to the oracle with the same boundary, over partial and several windows."""
+    h = tile // 2
+    T0 = problems.heat_sine_noise(N, seed=tile + N).astype(dtype)
+    for steps in sorted({1, h, h + 1, 3 * h + 5}):
+        sw, r = heat_gpu(T0, 0.2, steps, tile, "swept", bc=bc, bcv=bcv)
+        st, _ = heat_gpu(T0, 0.2, steps, tile, "standard", bc=bc, bcv=bcv)
+        assert np.array_equal(sw, st), (bc, tile, N, steps)
+        ref = oracle.heat_run(T0, r, steps, bc=bc, bcv=bcv)
+        assert rel_err(sw, ref) <= (1e-10 if dtype == np.float64 else 1e-6)
+        if steps > 1:
+            assert rel_err(ref, oracle.heat_run(T0, r, steps)) > 1e-6  # the walls matter
+
+
+@pytest.mark.parametrize("bc", [1, 2])
+def test_boundaries_closed_form_4096(bc):
+    """4096^2 FP64, tile 64, 1000 steps: the discrete eigenmode of the walled operator
+    (Dirichlet 0: sin(pi p (i+1)/(N+1)); zero flux: cos(pi p (i+1/2)/N)) decays by its
+    closed-form factor G^M, sampled over the whole grid."""
+    N, M, p, q = 4096, 1000, 3, 5
+    i = np.arange(N)
+    if bc == 1:
+        fx, fy = np.sin(np.pi * p * (i + 1) / (N + 1)), np.sin(np.pi * q * (i + 1) / (N + 1))
+        lam = 4 * (np.sin(np.pi * p / (2 * (N + 1))) ** 2 + np.sin(np.pi * q / (2 * (N + 1))) ** 2)
+    else:
+        fx, fy = np.cos(np.pi * p * (i + 0.5) / N), np.cos(np.pi * q * (i + 0.5) / N)
+        lam = 4 * (np.sin(np.pi * p / (2 * N)) ** 2 + np.sin(np.pi * q / (2 * N)) ** 2)
+    T0 = np.outer(fy, fx)
+    sw, r = heat_gpu(T0, 0.2, M, 64, "swept", bc=bc)
+    exp = (1 - r * lam) ** M * T0
+    err = rel_err(sw, exp)
+    print(f"walls bc={bc} 4096^2 closed form: {err:.2e}")
+    assert err <= 1e-12
+
+
 def test_c1_config_fp64():
     """64^2, FP64, r = 0.2, 100 steps, sin sin + noise, 16x16 tiles (both solvers)."""
     T0 = problems.heat_sine_noise(64)

@@ -39,6 +39,17 @@ def test_swept_equals_standard_heat(N, b, L):
     assert np.array_equal(out, oracle.heat_run(T0, 0.2, L))
 
 
+@pytest.mark.parametrize("bc,bcv", [(1, 0.0), (1, 0.4), (2, 0.0)])
+@pytest.mark.parametrize("N,b,L", [(16, 8, 11), (24, 8, 9), (32, 16, 21), (36, 12, 14)])
+def test_swept_equals_standard_heat_walls(bc, bcv, N, b, L):
+    """Dirichlet and zero-flux walls: the unchanged swept schedule, with outside neighbours
+    read as ghost values, gives the walled Standard result bit for bit (every dependency of
+    a walled cell is one of its periodic dependencies)."""
+    T0 = problems.heat_sine_noise(N, seed=N + b + L)
+    out, _ = SweptSim(Geom(N, b, 1, L), "heat", {"r": 0.2, "bc": bc, "bcv": bcv}).run(T0)
+    assert np.array_equal(out, oracle.heat_run(T0, 0.2, L, bc=bc, bcv=bcv))
+
+
 def test_swept_equals_standard_heat_fp32():
     T0 = problems.heat_sine_noise(32).astype(np.float32)
     out, _ = SweptSim(Geom(32, 16, 1, 19), "heat", {"r": 0.2}, dtype=np.float32).run(T0)
