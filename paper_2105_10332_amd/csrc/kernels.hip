@@ -124,49 +124,61 @@ __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict
 // the same tree order, then one block combines the partials in order, so
 // results are reproducible run to run.
 
+// Maximum that propagates NaN (a non-finite rate must not be skipped by the max).
+__device__ __forceinline__ double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
+
+struct SumOp {
+    __device__ double operator()(double a, double b) const { return a + b; }
+};
+struct MaxOp {
+    __device__ double operator()(double a, double b) const { return nan_max(a, b); }
+};
+
+// Block reduction of one double per thread: a butterfly over the 64 lanes of
+// each wavefront (lane i combines with lane i ^ o, o = 32 ... 1; both partners
+// get the same value, so the order is fixed), then thread 0 combines the
+// waves' results in wave order.  red holds one value per wave.  The result is
+// valid in thread 0.
+template <class Op>
+__device__ __forceinline__ double block_reduce(double v, Op op, double* red)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = op(v, __shfl_xor(v, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double r = red[0];
+    if (threadIdx.x == 0)
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) r = op(r, red[w]);
+    return r;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) plane_sum_partials(const T* __restrict__ x, size_t NN, int chunk,
                                                           double* __restrict__ partials)
 {
-    __shared__ double red[256];
+    __shared__ double red[4];
     const int plane = blockIdx.y;
     const size_t begin = (size_t)blockIdx.x * chunk;
     const size_t end = begin + chunk < NN ? begin + chunk : NN;
     const T* p = x + plane * NN;
     double s = 0.0;
     for (size_t i = begin + threadIdx.x; i < end; i += blockDim.x) s += (double)p[i];
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[plane * gridDim.x + blockIdx.x] = red[0];
+    s = block_reduce(s, SumOp{}, red);
+    if (threadIdx.x == 0) partials[plane * gridDim.x + blockIdx.x] = s;
 }
-
-// Maximum that propagates NaN (a non-finite rate must not be skipped by the max).
-__device__ __forceinline__ double nan_max(double a, double b) { return (a != a || a > b) ? a : b; }
 
 __global__ void __launch_bounds__(256) combine_partials(const double* __restrict__ partials, int nparts, int op_max,
                                                         double* __restrict__ out)
 {
-    __shared__ double red[256];
+    __shared__ double red[4];
     const int plane = blockIdx.x;
     double s = op_max ? -INFINITY : 0.0;
     for (int i = threadIdx.x; i < nparts; i += blockDim.x) {
         const double v = partials[plane * nparts + i];
         s = op_max ? nan_max(v, s) : s + v;
     }
-    red[threadIdx.x] = s;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) {
-            const double o = red[threadIdx.x + w];
-            red[threadIdx.x] = op_max ? nan_max(o, red[threadIdx.x]) : red[threadIdx.x] + o;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) out[plane] = red[0];
+    s = op_max ? block_reduce(s, MaxOp{}, red) : block_reduce(s, SumOp{}, red);
+    if (threadIdx.x == 0) out[plane] = s;
 }
 
 // Per-block maximum of the CFL signal rate (|u|+c)/dx + (|v|+c)/dy, in double.
@@ -174,7 +186,7 @@ template <typename T>
 __global__ void __launch_bounds__(256) cfl_partials(const T* __restrict__ q, size_t NN, int chunk, double gamma,
                                                     double dx, double dy, double* __restrict__ partials)
 {
-    __shared__ double red[256];
+    __shared__ double red[4];
     const size_t begin = (size_t)blockIdx.x * chunk;
     const size_t end = begin + chunk < NN ? begin + chunk : NN;
     double m = -INFINITY;
@@ -187,13 +199,8 @@ __global__ void __launch_bounds__(256) cfl_partials(const T* __restrict__ q, siz
         const double s = (fabs(u) + c) / dx + (fabs(v) + c) / dy;
         m = nan_max(s, m);
     }
-    red[threadIdx.x] = m;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if ((int)threadIdx.x < w) red[threadIdx.x] = nan_max(red[threadIdx.x + w], red[threadIdx.x]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+    m = block_reduce(m, MaxOp{}, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = m;
 }
 
 // ------------------------------------------------------------------ launchers
