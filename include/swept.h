@@ -87,8 +87,11 @@ typedef struct {
  * SWEPT_BC_DIRICHLET (every neighbour outside the square reads the constant
  * boundary_value) and SWEPT_BC_NEUMANN (zero flux: an outside neighbour
  * reads the edge cell itself).  A cell's dependencies are then a subset of
- * its periodic ones, so the same shapes and phases apply unchanged.  Euler,
- * the adjoint and the batch take SWEPT_BC_PERIODIC only (SWEPT_ENOTSUP). */
+ * its periodic ones, so the same shapes and phases apply unchanged.  The
+ * heat adjoint takes the walls too (the walled step is affine: lambda runs
+ * its homogeneous part, and dJ/dalpha pairs with the walled Laplacian
+ * including the ghosts).  Euler and the batch take SWEPT_BC_PERIODIC only
+ * (SWEPT_ENOTSUP). */
 #define SWEPT_BC_PERIODIC 0
 #define SWEPT_BC_DIRICHLET 1
 #define SWEPT_BC_NEUMANN 2

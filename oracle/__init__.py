@@ -70,6 +70,8 @@ def _declare(L):
         getattr(L, "oracle_heat_run" + s).argtypes = [_P, _P, _I, _D, _I]
         getattr(L, "oracle_heat_step_bc" + s).argtypes = [_P, _P, _I, _D, _I, _D]
         getattr(L, "oracle_heat_run_bc" + s).argtypes = [_P, _P, _I, _D, _I, _I, _D]
+        getattr(L, "oracle_heat_adjoint_bc" + s).argtypes = [_P, _P, _P, ctypes.POINTER(_D), _I, _D, _I, _P, _P,
+                                                             _I, _D]
         getattr(L, "oracle_heat_adjoint" + s).argtypes = [_P, _P, _P, ctypes.POINTER(_D), _I, _D, _I, _P, _P]
         getattr(L, "oracle_l2_mismatch" + s).argtypes = [_P, _P, _I]
         getattr(L, "oracle_l2_mismatch" + s).restype = _D
@@ -123,8 +125,8 @@ def heat_run(T0: np.ndarray, r: float, steps: int, bc: int = BC_PERIODIC, bcv: f
     return T
 
 
-def heat_adjoint(T0: np.ndarray, g: np.ndarray, r: float, steps: int):
-    """Discrete adjoint of ``heat_run``: returns (dJ/dT0, dJ/dr) for dJ/dT^M = g."""
+def heat_adjoint(T0: np.ndarray, g: np.ndarray, r: float, steps: int, bc: int = 0, bcv: float = 0.0):
+    """Discrete adjoint of ``heat_run``: returns (dJ/dT0, dJ/dr) for dJ/dT^M = g (bc, bcv: the walls)."""
     T0 = np.ascontiguousarray(T0)
     g = np.ascontiguousarray(g, dtype=T0.dtype)
     N = T0.shape[0]
@@ -132,8 +134,13 @@ def heat_adjoint(T0: np.ndarray, g: np.ndarray, r: float, steps: int):
     levels = np.empty((steps + 1, N, N), dtype=T0.dtype)
     work = np.empty_like(T0)
     dJdr = ctypes.c_double(0.0)
-    getattr(lib(), "oracle_heat_adjoint" + _sfx(T0))(_ptr(T0), _ptr(g), _ptr(out), ctypes.byref(dJdr), N,
-                                                     float(r), int(steps), _ptr(levels), _ptr(work))
+    if bc == BC_PERIODIC:
+        getattr(lib(), "oracle_heat_adjoint" + _sfx(T0))(_ptr(T0), _ptr(g), _ptr(out), ctypes.byref(dJdr), N,
+                                                         float(r), int(steps), _ptr(levels), _ptr(work))
+    else:
+        getattr(lib(), "oracle_heat_adjoint_bc" + _sfx(T0))(_ptr(T0), _ptr(g), _ptr(out), ctypes.byref(dJdr), N,
+                                                            float(r), int(steps), _ptr(levels), _ptr(work), int(bc),
+                                                            float(bcv))
     return out, dJdr.value
 
 

@@ -168,6 +168,45 @@ void NAME(oracle_heat_adjoint)(const REAL* T0, const REAL* g, REAL* gT0, double*
     *dJdr = acc;
 }
 
+/* L_bc T at cell (i, j) in double: the 5-point Laplacian (no 1/dx^2) with
+ * the boundary's neighbour values (Dirichlet ghosts at bcv, zero flux, or
+ * periodic), i.e. dT'/dr of the walled step T' = T + r L_bc T. */
+static double lap_at_bc(const REAL* T, int64_t N, int64_t i, int64_t j, int bc, REAL bcv)
+{
+    const double c = (double)T[j * N + i];
+    return ((double)neighbour(T, N, i + 1, j, i, j, bc, bcv) - 2.0 * c + (double)neighbour(T, N, i - 1, j, i, j, bc, bcv)) +
+           ((double)neighbour(T, N, i, j + 1, i, j, bc, bcv) - 2.0 * c + (double)neighbour(T, N, i, j - 1, i, j, bc, bcv));
+}
+
+/* Discrete adjoint of M walled heat steps.  The walled step is affine,
+ * T^{m+1} = A0 T^m + r b, with A0 = I + r L0 the step of the homogeneous
+ * wall (Dirichlet ghosts at 0, or zero flux) and b the ghost terms
+ * (bcv times the number of outside neighbours of a cell; 0 for zero flux).
+ * L0 is symmetric for both walls, so lambda^m = A0^T lambda^{m+1} is the
+ * homogeneous walled step applied to lambda, and
+ * dJ/dr = sum_{m<M} <lambda^{m+1}, L_bc T^m> with L_bc the walled Laplacian
+ * including the ghosts.  Arguments as oracle_heat_adjoint. */
+void NAME(oracle_heat_adjoint_bc)(const REAL* T0, const REAL* g, REAL* gT0, double* dJdr, int64_t N, double r,
+                                  int64_t M, REAL* levels, REAL* work, int64_t bc, double bcv_in)
+{
+    const int64_t NN = N * N;
+    const REAL bcv = (REAL)bcv_in;
+    memcpy(levels, T0, (size_t)NN * sizeof(REAL));
+    for (int64_t m = 0; m < M; ++m)
+        NAME(oracle_heat_step_bc)(levels + m * NN, levels + (m + 1) * NN, N, r, bc, bcv_in);
+    REAL* lam = gT0;
+    memcpy(lam, g, (size_t)NN * sizeof(REAL));
+    double acc = 0.0;
+    for (int64_t m = M - 1; m >= 0; --m) {
+        const REAL* Tm = levels + m * NN;
+        for (int64_t j = 0; j < N; ++j)
+            for (int64_t i = 0; i < N; ++i) acc += (double)lam[j * N + i] * lap_at_bc(Tm, N, i, j, (int)bc, bcv);
+        NAME(oracle_heat_step_bc)(lam, work, N, r, bc, 0.0); /* homogeneous wall: Dirichlet ghosts at 0 */
+        memcpy(lam, work, (size_t)NN * sizeof(REAL));
+    }
+    *dJdr = acc;
+}
+
 /* J = 1/2 sum (T - Tstar)^2 in double. */
 double NAME(oracle_l2_mismatch)(const REAL* T, const REAL* Tstar, int64_t n)
 {

@@ -35,15 +35,29 @@ namespace swept {
 
 // Forward level of the recompute: F(l) into `cur` (the LDS parity buffer)
 // and into the packed all-levels store `pk` (row-major over the footprint).
-template <typename T>
+// BC != 0 (windows that cross the domain edge of a walled problem): a
+// neighbour outside the square reads the ghost value (bcv for Dirichlet,
+// the cell itself for zero flux), as in the forward phases.
+template <typename T, int BC = 0>
 __device__ __forceinline__ void heat_level_pack(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ pk,
-                                                int W, const LevelEntry& e, T r)
+                                                int W, const LevelEntry& e, T r, int ox = 0, int oy = 0, int N = 0,
+                                                T bcv = T(0))
 {
     const int fw = e.fw, cells = fw * e.fh;
     for (int i = threadIdx.x; i < cells; i += blockDim.x) {
         const int q = qdiv(i, e.inv_fw);
-        const int li = (e.y0 + q) * W + (e.x0 + (i - q * fw));
-        const T v = heat_update<T>(prev[li], prev[li + 1], prev[li - 1], prev[li + W], prev[li - W], r);
+        const int lx = e.x0 + (i - q * fw), ly = e.y0 + q;
+        const int li = ly * W + lx;
+        const T c = prev[li];
+        T v;
+        if constexpr (BC != 0) {
+            const int gx = wrapi(ox + lx, N), gy = wrapi(oy + ly, N);
+            const T gh = BC == 1 ? bcv : c;
+            v = heat_update<T>(c, gx == N - 1 ? gh : prev[li + 1], gx == 0 ? gh : prev[li - 1],
+                               gy == N - 1 ? gh : prev[li + W], gy == 0 ? gh : prev[li - W], r);
+        } else {
+            v = heat_update<T>(c, prev[li + 1], prev[li - 1], prev[li + W], prev[li - W], r);
+        }
         cur[li] = v;
         pk[i] = v;
     }
@@ -58,11 +72,19 @@ __device__ __forceinline__ void heat_level_pack(const T* __restrict__ prev, T* _
 // WRAP = false when the window does not cross the periodic boundary.
 // Lambda has its own type L (double for both state precisions); T is the
 // forward state's type.
-template <typename L, typename T, bool T_GLOBAL, bool WRAP>
+//
+// Walls (BC != 0, only with WRAP): the walled step is affine, A0 T + r b, with
+// A0 the homogeneous walled step (symmetric) and b the Dirichlet ghost terms
+// (bcv times the number of outside neighbours).  Lambda runs A0: an outside
+// neighbour reads 0 (Dirichlet) or the cell itself (zero flux); the pairing
+// <lambda, L0 T + b> adds bcv * (outside neighbours) * lambda at edge cells.
+template <typename L, typename T, bool T_GLOBAL, bool WRAP, int BC = 0>
 __device__ __forceinline__ double lambda_level(const L* __restrict__ prev, L* __restrict__ cur,
                                                L* __restrict__ gout, const T* __restrict__ tsrc, int W, int C,
-                                               const LevelEntry& e, int hx2, int hy2, int ox, int oy, int N, L r)
+                                               const LevelEntry& e, int hx2, int hy2, int ox, int oy, int N, L r,
+                                               double bcv = 0.0)
 {
+    static_assert(BC == 0 || WRAP, "walls are met only by windows that cross the edge");
     const int fw = e.fw, cells = fw * e.fh;
     double acc = 0.0;
     for (int i = threadIdx.x; i < cells; i += blockDim.x) {
@@ -71,13 +93,24 @@ __device__ __forceinline__ double lambda_level(const L* __restrict__ prev, L* __
         const int li = ly * W + lx;
         const L c = prev[li];
         const L two_c = c + c;
-        const L dxx = (prev[li + 1] - two_c) + prev[li - 1];
-        const L dyy = (prev[li + W] - two_c) + prev[li - W];
+        const int gx = WRAP ? wrapi(ox + lx, N) : ox + lx, gy = WRAP ? wrapi(oy + ly, N) : oy + ly;
+        L xp = prev[li + 1], xm = prev[li - 1], yp = prev[li + W], ym = prev[li - W];
+        int nout = 0;
+        if constexpr (BC != 0) {
+            const L gh = BC == 1 ? L(0) : c;
+            nout = (gx == N - 1) + (gx == 0) + (gy == N - 1) + (gy == 0);
+            xp = gx == N - 1 ? gh : xp;
+            xm = gx == 0 ? gh : xm;
+            yp = gy == N - 1 ? gh : yp;
+            ym = gy == 0 ? gh : ym;
+        }
+        const L dxx = (xp - two_c) + xm;
+        const L dyy = (yp - two_c) + ym;
         const L v = (c + r * dxx) + r * dyy;  // the heat update (scheme.h) with its Laplacian kept
         cur[li] = v;
-        const int gx = WRAP ? wrapi(ox + lx, N) : ox + lx, gy = WRAP ? wrapi(oy + ly, N) : oy + ly;
         const T tv = T_GLOBAL ? tsrc[(size_t)gy * N + gx] : tsrc[i];
         acc += ((double)dxx + (double)dyy) * (double)tv;
+        if constexpr (BC == 1) acc += bcv * (double)nout * (double)c;
         const int dx = lx - C, dy = ly - C;
         if (!((dx >= -hx2) && (dx < hx2) && (dy >= -hy2) && (dy < hy2))) gout[(size_t)gy * N + gx] = v;
     }
@@ -121,7 +154,7 @@ __host__ __device__ inline AdjLds adjoint_lds_layout(size_t scalar, size_t lscal
 // reduction scratch), the packed forward levels (pk_max values) and their
 // offsets.  B > 0 fixes the tile edge at compile time (a.tile must equal
 // it), so the window pitch is an immediate LDS offset; B = 0 takes a.tile.
-template <typename T, int B>
+template <typename T, int B, int BC>
 __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk_max)
 {
     using L = double;  // lambda
@@ -185,9 +218,14 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
         preload_rings<HeatS, T>(tpar, P, src, W, P, W, N, NN, ox, oy, fx, fy, flo, fhi, h, C);
     }
     __syncthreads();
+    const T bcv = (T)a.p[1];  // Dirichlet ghost value, rounded as the forward phases round it
     for (int j = flo; j <= fhi; ++j) {
         const LevelEntry e = ftab[j - fkbase];
-        heat_level_pack<T>(tpar + ((j - 1) & 1) * P, tpar + (j & 1) * P, pk + offs[j], W, e, r);
+        if (BC != 0 && wraps)
+            heat_level_pack<T, BC>(tpar + ((j - 1) & 1) * P, tpar + (j & 1) * P, pk + offs[j], W, e, r, ox, oy, N,
+                                   bcv);
+        else
+            heat_level_pack<T>(tpar + ((j - 1) & 1) * P, tpar + (j & 1) * P, pk + offs[j], W, e, r);
         __syncthreads();
     }
 
@@ -224,9 +262,11 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
         const T* tglob = reinterpret_cast<const T*>(a.lvl0);
         if (wraps) {
             if (j >= 1)
-                acc += lambda_level<L, T, false, true>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N, rl);
+                acc += lambda_level<L, T, false, true, BC>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy,
+                                                           N, rl, (double)bcv);
             else
-                acc += lambda_level<L, T, true, true>(lprev, lcur, gout, tglob, W, C, e, hx2, hy2, ox, oy, N, rl);
+                acc += lambda_level<L, T, true, true, BC>(lprev, lcur, gout, tglob, W, C, e, hx2, hy2, ox, oy, N, rl,
+                                                          (double)bcv);
         } else {
             if (j >= 1)
                 acc += lambda_level<L, T, false, false>(lprev, lcur, gout, pk + offs[j], W, C, e, hx2, hy2, ox, oy, N,
@@ -244,9 +284,11 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
 // step per launch over the whole grid, lambda_out = A lambda_in (lambda in
 // double), with the pairing against the stored forward level T^m; per-block
 // partial sums.
-template <typename T>
+// BC: the wall (0 periodic, 1 Dirichlet with ghost value bcv, 2 zero flux),
+// handled as in lambda_level.
+template <typename T, int BC>
 __global__ void __launch_bounds__(256) adjoint_step_kernel(const double* __restrict__ lin, double* __restrict__ lout,
-                                                           const T* __restrict__ Tm, int N, double r,
+                                                           const T* __restrict__ Tm, int N, double r, double bcv,
                                                            double* __restrict__ partials)
 {
     __shared__ double red[256];
@@ -257,10 +299,22 @@ __global__ void __launch_bounds__(256) adjoint_step_kernel(const double* __restr
         const size_t row = (size_t)y * N;
         const double c = lin[i];
         const double two_c = c + c;
-        const double dxx = (lin[row + wrapi(x + 1, N)] - two_c) + lin[row + wrapi(x - 1, N)];
-        const double dyy = (lin[(size_t)wrapi(y + 1, N) * N + x] - two_c) + lin[(size_t)wrapi(y - 1, N) * N + x];
+        double xp = lin[row + wrapi(x + 1, N)], xm = lin[row + wrapi(x - 1, N)];
+        double yp = lin[(size_t)wrapi(y + 1, N) * N + x], ym = lin[(size_t)wrapi(y - 1, N) * N + x];
+        int nout = 0;
+        if constexpr (BC != 0) {
+            const double gh = BC == 1 ? 0.0 : c;
+            nout = (x == N - 1) + (x == 0) + (y == N - 1) + (y == 0);
+            xp = x == N - 1 ? gh : xp;
+            xm = x == 0 ? gh : xm;
+            yp = y == N - 1 ? gh : yp;
+            ym = y == 0 ? gh : ym;
+        }
+        const double dxx = (xp - two_c) + xm;
+        const double dyy = (yp - two_c) + ym;
         lout[i] = (c + r * dxx) + r * dyy;
         acc += (dxx + dyy) * (double)Tm[i];
+        if constexpr (BC == 1) acc += bcv * (double)nout * c;
     }
     const double tot = block_sum(acc, red);
     if (threadIdx.x == 0) partials[blockIdx.x] = tot;
@@ -300,22 +354,32 @@ hipError_t launch_lambda_convert(int dtype, const void* src, void* dst, size_t n
     return hipGetLastError();
 }
 
-// The reverse kernel for a tile: fixed-tile copies at b = 16 and 32, else the runtime-tile one.
-template <typename T>
-static const void* adjoint_kernel(int tile)
+// The reverse kernel for a tile and wall: fixed-tile copies at b = 16 and 32,
+// else the runtime-tile one.
+template <typename T, int BC>
+static const void* adjoint_kernel_bc(int tile)
 {
-    if (tile == 32) return (const void*)adjoint_phase_kernel<T, 32>;
-    if (tile == 16) return (const void*)adjoint_phase_kernel<T, 16>;
-    return (const void*)adjoint_phase_kernel<T, 0>;
+    if (tile == 32) return (const void*)adjoint_phase_kernel<T, 32, BC>;
+    if (tile == 16) return (const void*)adjoint_phase_kernel<T, 16, BC>;
+    return (const void*)adjoint_phase_kernel<T, 0, BC>;
+}
+
+template <typename T>
+static const void* adjoint_kernel(int tile, int bc)
+{
+    if (bc == 1) return adjoint_kernel_bc<T, 1>(tile);
+    if (bc == 2) return adjoint_kernel_bc<T, 2>(tile);
+    return adjoint_kernel_bc<T, 0>(tile);
 }
 
 hipError_t set_adjoint_lds_limit(int dtype, size_t lds)
 {
     hipError_t e = hipSuccess;
-    for (int tile : {0, 16, 32})
-        if (e == hipSuccess)
-            e = hipFuncSetAttribute(dtype == 0 ? adjoint_kernel<double>(tile) : adjoint_kernel<float>(tile),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    for (int bc = 0; bc < 3; ++bc)
+        for (int tile : {0, 16, 32})
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(dtype == 0 ? adjoint_kernel<double>(tile, bc) : adjoint_kernel<float>(tile, bc),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return e;
 }
 
@@ -324,19 +388,33 @@ hipError_t launch_adjoint_phase(int dtype, const PhaseArgs& a, int pk_max, int w
     const int t2 = a.tiles * a.tiles;
     const int nblk = (a.phase & 1) ? 2 * t2 : t2;
     void* args[] = {(void*)&a, (void*)&pk_max};
-    return hipLaunchKernel(dtype == 0 ? adjoint_kernel<double>(a.tile) : adjoint_kernel<float>(a.tile), dim3(nblk),
-                           dim3(wg), args, lds, st);
+    return hipLaunchKernel(dtype == 0 ? adjoint_kernel<double>(a.tile, a.bc) : adjoint_kernel<float>(a.tile, a.bc),
+                           dim3(nblk), dim3(wg), args, lds, st);
 }
 
-hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const void* Tm, int N, double r,
-                               double* partials, int nblocks, hipStream_t st)
+template <typename T, int BC>
+static void adjoint_step_launch(const void* lin, void* lout, const void* Tm, int N, double r, double bcv,
+                                double* partials, int nblocks, hipStream_t st)
 {
-    if (dtype == 0)
-        hipLaunchKernelGGL(adjoint_step_kernel<double>, dim3(nblocks), dim3(256), 0, st, (const double*)lin,
-                           (double*)lout, (const double*)Tm, N, r, partials);
-    else  // the forward ran with r rounded to float; lambda runs the transpose of that operator
-        hipLaunchKernelGGL(adjoint_step_kernel<float>, dim3(nblocks), dim3(256), 0, st, (const double*)lin,
-                           (double*)lout, (const float*)Tm, N, (double)(float)r, partials);
+    hipLaunchKernelGGL((adjoint_step_kernel<T, BC>), dim3(nblocks), dim3(256), 0, st, (const double*)lin,
+                       (double*)lout, (const T*)Tm, N, r, bcv, partials);
+}
+
+hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const void* Tm, int N, double r, int bc,
+                               double bcv, double* partials, int nblocks, hipStream_t st)
+{
+    // FP32: the forward ran with r and the ghost value rounded to float; lambda runs the
+    // transpose of that operator and pairs with those ghosts
+    const double rr = dtype == 0 ? r : (double)(float)r, gv = dtype == 0 ? bcv : (double)(float)bcv;
+    if (dtype == 0) {
+        if (bc == 1) adjoint_step_launch<double, 1>(lin, lout, Tm, N, rr, gv, partials, nblocks, st);
+        else if (bc == 2) adjoint_step_launch<double, 2>(lin, lout, Tm, N, rr, gv, partials, nblocks, st);
+        else adjoint_step_launch<double, 0>(lin, lout, Tm, N, rr, gv, partials, nblocks, st);
+    } else {
+        if (bc == 1) adjoint_step_launch<float, 1>(lin, lout, Tm, N, rr, gv, partials, nblocks, st);
+        else if (bc == 2) adjoint_step_launch<float, 2>(lin, lout, Tm, N, rr, gv, partials, nblocks, st);
+        else adjoint_step_launch<float, 0>(lin, lout, Tm, N, rr, gv, partials, nblocks, st);
+    }
     return hipGetLastError();
 }
 

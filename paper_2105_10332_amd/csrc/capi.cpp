@@ -398,7 +398,6 @@ static int tape_check(const swept_ctx* c, int64_t n_steps, TapePlan* t)
 {
     if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
     if (c->prob.kind != SWEPT_HEAT) return fail(SWEPT_ENOTSUP, "the adjoint is implemented for heat only");
-    if (c->prob.boundary != SWEPT_BC_PERIODIC) return fail(SWEPT_ENOTSUP, "the adjoint is periodic only");
     if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
     if (c->adj_lds == 0)
         return fail(SWEPT_ESHAPE, "tile %d too large for the adjoint's LDS (all levels of a shape are kept)",
@@ -465,10 +464,10 @@ int swept_adjoint(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes
         e = hipMemcpyAsync(stash, ck(t.cycles), SB, hipMemcpyDeviceToDevice, st);
         for (int64_t m = 1; m < t.rem && e == hipSuccess; ++m)
             e = swept::launch_heat_standard(c->prob.dtype, stash + S * (m - 1), stash + S * m, N, c->d.r,
-                                            SWEPT_BC_PERIODIC, 0.0, st);
+                                            c->prob.boundary, c->c[1], st);
         for (int64_t m = t.rem - 1; m >= 0 && e == hipSuccess; --m) {
-            e = swept::launch_adjoint_step(c->prob.dtype, La, Lb, stash + S * m, N, c->d.r, parts + pslot,
-                                           t.std_blocks, st);
+            e = swept::launch_adjoint_step(c->prob.dtype, La, Lb, stash + S * m, N, c->d.r, c->prob.boundary,
+                                           c->c[1], parts + pslot, t.std_blocks, st);
             pslot += t.std_blocks;
             void* tmp = La;
             La = Lb;

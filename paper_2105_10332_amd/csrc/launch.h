@@ -74,8 +74,8 @@ hipError_t launch_euler_standard(int dtype, const void* in, void* out, const Std
 size_t adjoint_lds(int dtype, int tile, int pk_max, int wg);
 hipError_t set_adjoint_lds_limit(int dtype, size_t lds);
 hipError_t launch_adjoint_phase(int dtype, const PhaseArgs& a, int pk_max, int wg, size_t lds, hipStream_t st);
-hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const void* Tm, int N, double r,
-                               double* partials, int nblocks, hipStream_t st);
+hipError_t launch_adjoint_step(int dtype, const void* lin, void* lout, const void* Tm, int N, double r, int bc,
+                               double bcv, double* partials, int nblocks, hipStream_t st);
 // lambda (double) from/to the state's type: widen = true copies a state-typed
 // field into double, false the reverse.
 hipError_t launch_lambda_convert(int dtype, const void* src, void* dst, size_t n, bool widen, hipStream_t st);

@@ -181,15 +181,17 @@ class SweptHeatAdvance(torch.autograd.Function):
     """T^M = swept heat advance of T^0 by n_steps with diffusivity alpha, differentiable
     in T^0 and alpha through the hand-written swept adjoint (swept_adjoint).
 
-    apply(T0, alpha, n_steps, dt, length=1.0, tile=0): T0 an (N, N) GPU tensor,
-    alpha a 0-d tensor (or float).  The forward records a checkpoint per swept
-    cycle; backward runs the reverse sweep and returns (dJ/dT0, dJ/dalpha)."""
+    apply(T0, alpha, n_steps, dt, length=1.0, tile=0, boundary=BC_PERIODIC, boundary_value=0.0):
+    T0 an (N, N) GPU tensor, alpha a 0-d tensor (or float), boundary/boundary_value the
+    walls (swept.h).  The forward records a checkpoint per swept cycle; backward runs the
+    reverse sweep and returns (dJ/dT0, dJ/dalpha)."""
 
     @staticmethod
-    def forward(ctx, T0, alpha, n_steps, dt, length=1.0, tile=0):
+    def forward(ctx, T0, alpha, n_steps, dt, length=1.0, tile=0, boundary=BC_PERIODIC, boundary_value=0.0):
         state = T0.detach().clone().contiguous()
         a = float(alpha)
-        solver = SweptSolver(HEAT, state, dt=dt, length=length, alpha=a, tile=tile)
+        solver = SweptSolver(HEAT, state, dt=dt, length=length, alpha=a, tile=tile, boundary=boundary,
+                             boundary_value=boundary_value)
         tape = solver.new_tape(n_steps)
         solver.swept_advance_checkpointed(n_steps, tape)
         ctx.solver, ctx.tape, ctx.n = solver, tape, int(n_steps)
@@ -207,7 +209,7 @@ class SweptHeatAdvance(torch.autograd.Function):
         if ctx.alpha_is_tensor:
             shape, dtype, device = ctx.alpha_meta
             ga = torch.full(shape, dalpha, dtype=dtype, device=device)
-        return gT0, ga, None, None, None, None
+        return gT0, ga, None, None, None, None, None, None
 
 
 def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 1.4) -> float:
