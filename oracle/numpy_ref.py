@@ -59,24 +59,25 @@ def laplacian(T: np.ndarray) -> np.ndarray:
 
 
 def _pressure(Q, gm1):
-    u = Q[1] / Q[0]
-    v = Q[2] / Q[0]
+    inv = Q.dtype.type(1) / Q[0]
+    u = Q[1] * inv
+    v = Q[2] * inv
     return gm1 * (Q[3] - Q.dtype.type(0.5) * (Q[1] * u + Q[2] * v))
 
 
 def _phys_flux(Q, a, gamma, gm1):
     """Physical flux along the axis whose momentum is Q[a]; returns (F, |u_a| + c)."""
     b = 2 if a == 1 else 1
-    rho = Q[0]
-    ua = Q[a] / rho
-    ub = Q[b] / rho
+    inv = Q.dtype.type(1) / Q[0]
+    ua = Q[a] * inv
+    ub = Q[b] * inv
     p = gm1 * (Q[3] - Q.dtype.type(0.5) * (Q[a] * ua + Q[b] * ub))
     F = np.empty_like(Q)
     F[0] = Q[a]
     F[a] = Q[a] * ua + p
     F[b] = Q[a] * ub
     F[3] = (Q[3] + p) * ua
-    c = np.sqrt(gamma * p / rho)
+    c = np.sqrt(gamma * p * inv)
     return F, np.abs(ua) + c
 
 
@@ -85,10 +86,11 @@ def _roe_speed(L, R, a, gm1):
     b = 2 if a == 1 else 1
     t = L.dtype.type
     wl, wr = np.sqrt(L[0]), np.sqrt(R[0])
-    ual, ubl = L[a] / L[0], L[b] / L[0]
-    uar, ubr = R[a] / R[0], R[b] / R[0]
-    hl = (L[3] + _pressure(L, gm1)) / L[0]
-    hr = (R[3] + _pressure(R, gm1)) / R[0]
+    il, ir = t(1) / L[0], t(1) / R[0]
+    ual, ubl = L[a] * il, L[b] * il
+    uar, ubr = R[a] * ir, R[b] * ir
+    hl = (L[3] + _pressure(L, gm1)) * il
+    hr = (R[3] + _pressure(R, gm1)) * ir
     ua = (wl * ual + wr * uar) / (wl + wr)
     ub = (wl * ubl + wr * ubr) / (wl + wr)
     H = (wl * hl + wr * hr) / (wl + wr)
@@ -104,16 +106,18 @@ def _face_flux(Q, axis, gamma, scheme=0):
     shift = (lambda A, k: _sh(A, k, 0)) if axis == "x" else (lambda A, k: _sh(A, 0, k))
     p = _pressure(Q, gm1)
     with np.errstate(divide="ignore", invalid="ignore"):
-        ratio = (shift(p, 1) - p) / (p - shift(p, -1))  # ratio at every cell
-        rB = ratio
-        rC = shift(ratio, 1)
-        okB = (rB > 0) & (rB < np.inf)
+        # face between B (this cell) and C (its +axis neighbour): 1/r_B and r_C through 1/(pC - pB)
+        pA, pB, pC, pD = shift(p, -1), p, shift(p, 1), shift(p, 2)
+        inv_d = t(1) / (pC - pB)
+        iB = (pB - pA) * inv_d
+        rC = (pD - pC) * inv_d
+        okB = (iB > 0) & (iB < np.inf)
         okC = (rC > 0) & (rC < np.inf)
         if scheme & 1:
-            phiL = t(0.5) * np.minimum(rB, t(1))
+            phiL = t(0.5) * np.minimum(t(1) / iB, t(1))
             phiR = t(0.5) * np.minimum(t(1) / rC, t(1))
         else:
-            phiL = t(0.5) * np.minimum(t(1) / rB, t(1))
+            phiL = t(0.5) * np.minimum(iB, t(1))
             phiR = t(0.5) * np.minimum(rC, t(1))
     B = Q
     C = shift(Q, 1)
