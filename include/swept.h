@@ -90,8 +90,8 @@ typedef struct {
  * its periodic ones, so the same shapes and phases apply unchanged.  The
  * heat adjoint takes the walls too (the walled step is affine: lambda runs
  * its homogeneous part, and dJ/dalpha pairs with the walled Laplacian
- * including the ghosts).  Euler and the batch take SWEPT_BC_PERIODIC only
- * (SWEPT_ENOTSUP). */
+ * including the ghosts), and so does the batch.  Euler takes
+ * SWEPT_BC_PERIODIC only (SWEPT_ENOTSUP). */
 #define SWEPT_BC_PERIODIC 0
 #define SWEPT_BC_DIRICHLET 1
 #define SWEPT_BC_NEUMANN 2
@@ -104,7 +104,7 @@ typedef struct {
  * |u_R|+c_R).  SWEPT_LIMITER_LITERAL takes the factors with the exponents as
  * printed, min(r_i,1)/2 and min(1/r_{i+1},1)/2.  SWEPT_SPEED_ROE takes s =
  * |u~|+c~ at the Roe-averaged state of Q_L and Q_R.  Bits combine.  The
- * single-problem calls accept every combination; the batch accepts 0 only. */
+ * single-problem calls and the batch accept every combination. */
 #define SWEPT_LIMITER_LITERAL 1
 #define SWEPT_SPEED_ROE 2
 

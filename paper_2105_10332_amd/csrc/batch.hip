@@ -27,6 +27,25 @@ __device__ __forceinline__ int problem_phases(const PhaseArgs& a, long long n_st
     return L > 0 ? 2 * (int)((L + a.h - 1) / a.h) + 1 : 0;
 }
 
+// One shape instance of problem a: the kernel variant its kind, wall and
+// scheme bits select (the same device function as the single-problem kernels).
+template <typename T>
+__device__ __forceinline__ void instance(const PhaseArgs& a, int blk, unsigned char* smem_raw)
+{
+    if (a.kind == 0) {
+        if (a.bc == 1) phase_instance<HeatSV<1>, T>(a, blk, smem_raw);
+        else if (a.bc == 2) phase_instance<HeatSV<2>, T>(a, blk, smem_raw);
+        else phase_instance<HeatS, T>(a, blk, smem_raw);
+    } else {
+        switch (a.scheme) {
+            case 1: phase_instance<EulerSV<1>, T>(a, blk, smem_raw); break;
+            case 2: phase_instance<EulerSV<2>, T>(a, blk, smem_raw); break;
+            case 3: phase_instance<EulerSV<3>, T>(a, blk, smem_raw); break;
+            default: phase_instance<EulerS, T>(a, blk, smem_raw);
+        }
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
     batch_kernel(const PhaseArgs* __restrict__ probs, int count, int nphase_max, long long n_steps, int* ctr)
@@ -68,8 +87,7 @@ __global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
             PhaseArgs a = probs[lo];
             a.phase = gp;
             a.L = (int)(n_steps * (a.kind == 0 ? 1 : 2));
-            if (a.kind == 0) phase_instance<HeatS, T>(a, it - pre[lo], smem_raw);
-            else phase_instance<EulerS, T>(a, it - pre[lo], smem_raw);
+            instance<T>(a, it - pre[lo], smem_raw);
             __syncthreads();
         }
         grid.sync();

@@ -638,9 +638,6 @@ int batch_derive(const swept_problem* probs, const swept_tuning* tunes, int32_t 
     size_t off = 0;
     for (int q = 0; q < count; ++q) {
         if (probs[q].dtype != probs[0].dtype) return fail(SWEPT_EINVAL, "all problems of a batch share one dtype");
-        if (probs[q].scheme != 0) return fail(SWEPT_ENOTSUP, "problem %d: the batch runs scheme 0 only", q);
-        if (probs[q].boundary != SWEPT_BC_PERIODIC)
-            return fail(SWEPT_ENOTSUP, "problem %d: the batch is periodic only", q);
         swept_tuning t{tunes ? tunes[q].tile : 0, swept::batch_wg(probs[0].dtype)};
         const int rc = derive(&probs[q], &t, &(*d)[q]);
         if (rc) return rc;
@@ -711,9 +708,12 @@ int swept_batch_init(swept_batch** ctx, const swept_problem* probs, const swept_
         a.h = d[q].h;
         a.tiles = probs[q].nx / d[q].tile;
         a.kind = probs[q].kind;
+        a.scheme = probs[q].scheme;
+        a.bc = probs[q].boundary;
         a.tab = reinterpret_cast<swept::LevelEntry*>(w + lay.tab_off[q]);
         if (probs[q].kind == SWEPT_HEAT) {
             a.p[0] = d[q].r;
+            a.p[1] = probs[q].boundary == SWEPT_BC_DIRICHLET ? probs[q].boundary_value : 0.0;
         } else {
             a.p[0] = probs[q].gamma;
             a.p[1] = 0.5 * probs[q].dt / d[q].dx;

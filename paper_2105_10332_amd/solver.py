@@ -131,15 +131,18 @@ class SweptBatch:
     """Many problems (heat (N, N) and Euler (4, N, N) tensors, one dtype) advanced
     together by one persistent launch per swept_batch_advance (see swept.h).
 
-    items: list of (kind, state, dt, length, alpha, gamma, tile)."""
+    items: list of (kind, state, dt, length, alpha, gamma, tile), optionally followed by
+    (scheme, boundary, boundary_value) as for SweptSolver."""
 
     def __init__(self, items):
         n = len(items)
         self.states = [it[1] for it in items]
         probs = (Problem * n)()
         tunes = (Tuning * n)()
-        for q, (kind, st, dt, length, alpha, gamma, tile) in enumerate(items):
-            probs[q] = make_problem(kind, st.shape[-1], st.dtype, dt, length, alpha, gamma)
+        for q, (kind, st, dt, length, alpha, gamma, tile, *extra) in enumerate(items):
+            scheme, boundary, boundary_value = (list(extra) + [0, 0, 0.0][len(extra):])[:3]
+            probs[q] = make_problem(kind, st.shape[-1], st.dtype, dt, length, alpha, gamma, scheme, boundary,
+                                    boundary_value)
             tunes[q] = Tuning(int(tile), 0)
         out = ctypes.c_size_t(0)
         check(lib().swept_batch_workspace_bytes(probs, tunes, n, ctypes.byref(out)))

@@ -47,6 +47,37 @@ def test_batch_equals_standalone(dtype, steps):
     assert b.grid >= 256
 
 
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_batch_walls_and_scheme_variants(dtype):
+    """Walled heat problems and Euler scheme variants in one launch: each equals its own
+    swept advance bit for bit, and (FP64) the oracle with the same wall or variant."""
+    spec = [(HEAT, 64, 16, 0.2, (0, 1, 0.5)), (HEAT, 96, 32, 0.1, (0, 2, 0.0)), (HEAT, 64, 64 // 2, 0.24, (0, 0, 0.0)),
+            (EULER, 64, 16, 5.0, (1, 0, 0.0)), (EULER, 48, 8, 2.0, (2, 0, 0.0)), (EULER, 64, 32, 3.0, (3, 0, 0.0))]
+    items = [it + spec[q][4] for q, it in enumerate(_items(dtype, [s[:4] for s in spec]))]
+    init = [it[1].cpu().numpy().copy() for it in items]
+    refs = []
+    for kind, x, dt, length, alpha, gamma, tile, scheme, bc, bcv in items:
+        y = x.clone()
+        s = SweptSolver(kind, y, dt=dt, length=length, alpha=alpha, gamma=gamma, tile=tile, scheme=scheme,
+                        boundary=bc, boundary_value=bcv)
+        s.swept_advance(17)
+        s.close()
+        refs.append(y)
+    b = SweptBatch(items)
+    b.swept_batch_advance(17)
+    torch.cuda.synchronize()
+    for q, (it, y) in enumerate(zip(items, refs)):
+        assert torch.equal(it[1], y), (q, spec[q])
+        if dtype == torch.float64:
+            kind, x, dt, _, _, _, _, scheme, bc, bcv = it
+            n = x.shape[-1]
+            if kind == HEAT:
+                ref = oracle.heat_run(init[q], b.info(q).r, 17, bc=bc, bcv=bcv)
+            else:
+                ref = oracle.euler_run(init[q], dt, 10 / n, 10 / n, 1.4, 17, scheme=scheme)
+            assert rel_err(x.cpu().numpy(), ref) <= 1e-10, q
+
+
 def test_batch_vs_oracle_and_twice():
     """Two consecutive batch advances (state carried over) against the oracle."""
     items = _items(torch.float64, SPEC[:4])
