@@ -121,23 +121,25 @@ def _vortex_gpu(n, dtype, length=10.0, eps=5.0, gamma=GAMMA, rows=4096):
     return Q
 
 
-def test_largest_grid_sampled_cells():
+@pytest.mark.parametrize("scheme", [0, 3])
+def test_largest_grid_sampled_cells(scheme):
     """The largest grid the library accepts (32768^2, FP32: 2^32 values over the four
-    planes), in the FP32 launch configuration (b = 32, 512 threads), three steps: Swept equals
-    Standard bit for bit, and sampled cells in and around the vortex core equal the oracle
-    run on a 40 x 40 periodic patch around each (a cell after three RK2 steps depends only on
-    cells within 12 of it, so the patch's own wrap cannot reach the centre)."""
+    planes), in the FP32 launch configuration (b = 32, 512 threads), three steps, default
+    scheme and both variant bits: Swept equals Standard bit for bit, and sampled cells in and
+    around the vortex core equal the oracle run on a 40 x 40 periodic patch around each (a cell
+    after three RK2 steps depends only on cells within 12 of it, so the patch's own wrap cannot
+    reach the centre)."""
     n, M, tile, wg = 32768, 3, 32, 512
     dx = 10.0 / n
     dt = 0.4 * dx / 6.5  # below the CFL limit: (|u|+c) + (|v|+c) < 6.5 everywhere on this vortex
     Q0 = _vortex_gpu(n, torch.float32)
     Q = Q0.clone()
-    s = SweptSolver(EULER, Q, dt=dt, length=10.0, gamma=GAMMA, tile=tile, wg=wg)
+    s = SweptSolver(EULER, Q, dt=dt, length=10.0, gamma=GAMMA, tile=tile, wg=wg, scheme=scheme)
     s.swept_advance(M)
     s.close()
     del s
     Qs = Q0.clone()
-    s = SweptSolver(EULER, Qs, dt=dt, length=10.0, gamma=GAMMA, tile=tile, wg=wg)
+    s = SweptSolver(EULER, Qs, dt=dt, length=10.0, gamma=GAMMA, tile=tile, wg=wg, scheme=scheme)
     s.standard_advance(M)
     torch.cuda.synchronize()
     s.close()
@@ -153,10 +155,10 @@ def test_largest_grid_sampled_cells():
         iy = torch.tensor((np.arange(-20, 20) + cy) % n, device=DEV)
         ix = torch.tensor((np.arange(-20, 20) + cx) % n, device=DEV)
         patch = Q0[:, iy][:, :, ix].cpu().numpy()
-        ref = oracle.euler_run(patch, dt, dx, dx, GAMMA, M)[:, 20, 20]
+        ref = oracle.euler_run(patch, dt, dx, dx, GAMMA, M, scheme=scheme)[:, 20, 20]
         got = Q[:, int(cy), int(cx)].cpu().numpy()
         worst = max(worst, float(np.max(np.abs(got.astype(np.float64) - ref) / scale)))
-    print(f"Euler {n}^2 fp32 sampled cells vs oracle patches: {worst:.3e}")
+    print(f"Euler {n}^2 fp32 scheme {scheme} sampled cells vs oracle patches: {worst:.3e}")
     assert worst <= 1e-6
 
 

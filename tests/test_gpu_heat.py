@@ -184,6 +184,56 @@ def test_largest_grid_closed_form(dtype):
     assert err < (1e-13 if dtype == np.float64 else 1e-5)
 
 
+@pytest.mark.parametrize("bc", [1, 2])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_largest_grid_walls_closed_form(bc, dtype):
+    """Walls at the largest grid (32768^2, tile 64, 37 steps ending mid-window): Swept equals
+    Standard, and sampled cells (including the four edges) equal the walled operator's
+    eigenmode decay G^M: sin(pi p (i+1)/(N+1)) for Dirichlet 0, cos(pi p (i+1/2)/N) for zero
+    flux."""
+    import torch
+
+    from gpu_helpers import DEV, TDT
+    from paper_2105_10332_amd.solver import HEAT, SweptSolver
+
+    n, M, r, tile, p, q = 32768, 37, 0.2, 64, 3, 5
+    i = torch.arange(n, device=DEV, dtype=torch.float64)
+    if bc == 1:
+        fx, fy = torch.sin(math.pi * p * (i + 1) / (n + 1)), torch.sin(math.pi * q * (i + 1) / (n + 1))
+    else:
+        fx, fy = torch.cos(math.pi * p * (i + 0.5) / n), torch.cos(math.pi * q * (i + 0.5) / n)
+    T0 = (fy[:, None] * fx[None, :]).to(TDT[dtype])
+    del i, fx, fy
+    T = T0.clone()
+    dx = 1.0 / n
+    s = SweptSolver(HEAT, T, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, boundary=bc)
+    s.swept_advance(M)
+    r_used = s.info.r
+    s.close()
+    del s
+    Ts = T0.clone()
+    s = SweptSolver(HEAT, Ts, dt=r * dx * dx, length=1.0, alpha=1.0, tile=tile, boundary=bc)
+    s.standard_advance(M)
+    torch.cuda.synchronize()
+    s.close()
+    del s
+    assert torch.equal(T, Ts)
+    del Ts, T0
+    rng = np.random.default_rng(12)
+    js = np.concatenate([rng.integers(0, n, 300), [0, n - 1, 0, n - 1, 7, n - 3]])
+    is_ = np.concatenate([rng.integers(0, n, 300), [0, n - 1, n - 1, 0, n - 1, 0]])
+    got = T[torch.tensor(js, device=DEV), torch.tensor(is_, device=DEV)].double().cpu().numpy()
+    if bc == 1:
+        lam = 4 * (math.sin(math.pi * p / (2 * (n + 1))) ** 2 + math.sin(math.pi * q / (2 * (n + 1))) ** 2)
+        mode = np.sin(np.pi * q * (js + 1) / (n + 1)) * np.sin(np.pi * p * (is_ + 1) / (n + 1))
+    else:
+        lam = 4 * (math.sin(math.pi * p / (2 * n)) ** 2 + math.sin(math.pi * q / (2 * n)) ** 2)
+        mode = np.cos(np.pi * q * (js + 0.5) / n) * np.cos(np.pi * p * (is_ + 0.5) / n)
+    err = np.abs(got - (1 - r_used * lam) ** M * mode).max()
+    print(f"walls bc={bc} {n}^2 {np.dtype(dtype).name}: closed-form error {err:.3e}")
+    assert err < (1e-13 if dtype == np.float64 else 1e-5)
+
+
 def test_nonfinite_state_is_reported():
     """swept_conserved reports a non-finite plane sum as SWEPT_ENONFINITE (after a swept
     advance has spread a NaN), instead of returning it as a number."""
