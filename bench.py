@@ -82,7 +82,8 @@ def parse():
     ap.add_argument("--wg", type=int, default=0, help="0: tuned or library default")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--boundary", type=int, default=0,
-                    help="heat boundary: 0 periodic, 1 Dirichlet (ghost value --boundary-value), 2 zero flux")
+                    help="0 periodic; heat 1 Dirichlet (ghost value --boundary-value), 2 zero flux; "
+                         "Euler 2 zero gradient, 3 slip walls")
     ap.add_argument("--boundary-value", type=float, default=0.0)
     ap.add_argument("--scheme", type=int, default=0,
                     help="Euler scheme variant bits: 1 limiter factors as printed, 2 Roe-averaged speed")
@@ -137,20 +138,20 @@ def cpu_heat(dtype_np, n, r, budget_s=25.0, bc=0, bcv=0.0):
                       f"(OpenMP over rows), {el:.1f} s"}
 
 
-def cpu_euler(dtype_np, n, dt, budget_s=15.0, scheme=0):
+def cpu_euler(dtype_np, n, dt, budget_s=15.0, scheme=0, bc=0):
     import numpy as np
 
     import oracle
     from paper_2105_10332_amd import problems
 
     Q0 = problems.shu_vortex(n).astype(dtype_np)
-    Q1 = oracle.euler_run(Q0, dt, 10 / n, 10 / n, 1.4, 1, scheme)
+    Q1 = oracle.euler_run(Q0, dt, 10 / n, 10 / n, 1.4, 1, scheme, bc)
     t = time.perf_counter()
-    Q1 = oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, 2, scheme)
+    Q1 = oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, 2, scheme, bc)
     one = (time.perf_counter() - t) / 2
     k = max(1, min(1000, int(budget_s / max(one, 1e-6))))
     t = time.perf_counter()
-    oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, k, scheme)
+    oracle.euler_run(Q1, dt, 10 / n, 10 / n, 1.4, k, scheme, bc)
     el = time.perf_counter() - t
     return {"value": n * n * k / el, "unit": "cell-steps/s", "cores": cores(), "kind": "oracle",
             "sample": f"Euler vortex {n}x{n} {np.dtype(dtype_np).name}, {k} RK2 steps of the C oracle, {el:.1f} s"}
@@ -271,7 +272,8 @@ def run_euler(args):
     Q0 = problems.shu_vortex(n)
     q = torch.tensor(Q0, dtype=tdt, device="cuda")
     dt = swept_cfl_dt(torch.tensor(Q0, device="cuda"), 10.0, 0.4)
-    solver = SweptSolver(EULER, q, dt=dt, length=10.0, gamma=1.4, tile=tile, wg=wg, scheme=args.scheme)
+    solver = SweptSolver(EULER, q, dt=dt, length=10.0, gamma=1.4, tile=tile, wg=wg, scheme=args.scheme,
+                         boundary=args.boundary)
     for _ in range(args.warmup):
         solver.swept_advance(M)
     sec, wall = timed(lambda: solver.swept_advance(M), args.steps)
@@ -280,7 +282,8 @@ def run_euler(args):
     plan = geometry.totals(n, tile, 2, 2 * M, True)
     scheme = {0: "minmod + Rusanov", 1: "limiter factors as printed + Rusanov", 2: "minmod + Roe-averaged speed",
               3: "limiter factors as printed + Roe-averaged speed"}[args.scheme]
-    cfg = {"workload": f"Euler {n}x{n} periodic [0,10]^2, gamma 1.4, vortex eps 5 on (1,1), {scheme}, "
+    walls = {0: "periodic", 2: "zero-gradient walls", 3: "slip walls"}[args.boundary]
+    cfg = {"workload": f"Euler {n}x{n} {walls} [0,10]^2, gamma 1.4, vortex eps 5 on (1,1), {scheme}, "
                        f"RK2, CFL 0.4 (dt {dt:.6e}), {M} steps per bench step; swept tile {tile}",
            "tile": tile, "scheme": args.scheme, "time_steps_per_step": M, "launches_per_step": plan["launches"]}
     out = base_record(args, rate, "cell-steps/s", sec, dt_name, cfg)
@@ -288,7 +291,8 @@ def run_euler(args):
     out["roofline"] = roofline(plan, S, 4, plan["launches"] * args.steps, sec, "swept_phase_kernel<EulerS>")
     if not args.no_standard:
         st = torch.tensor(Q0, dtype=tdt, device="cuda")
-        ss = SweptSolver(EULER, st, dt=dt, length=10.0, gamma=1.4, tile=tile, scheme=args.scheme)
+        ss = SweptSolver(EULER, st, dt=dt, length=10.0, gamma=1.4, tile=tile, scheme=args.scheme,
+                         boundary=args.boundary)
         ss.standard_advance(M)
         ssec, _ = timed(lambda: ss.standard_advance(M), 1)
         out["standard"] = {"value": n * n * M / ssec, "unit": "cell-steps/s", "ms_per_advance": ssec * 1e3}
@@ -296,7 +300,8 @@ def run_euler(args):
     out["reductions"] = reductions(solver, q, S, n)
     out["wall_s"] = wall
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_euler(np.float64 if dt_name == "f64" else np.float32, n, dt, scheme=args.scheme)
+        out["cpu_baseline"] = cpu_euler(np.float64 if dt_name == "f64" else np.float32, n, dt, scheme=args.scheme,
+                                        bc=args.boundary)
     return out
 
 

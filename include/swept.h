@@ -78,7 +78,7 @@ typedef struct {
     double alpha;   /* heat diffusivity; r = alpha*dt/dx^2 with dx = lx/nx    */
     double gamma;   /* Euler ratio of specific heats (> 1)                    */
     int32_t scheme; /* Euler scheme variant bits (0 for heat), see below       */
-    int32_t boundary; /* SWEPT_BC_*: periodic (0) or, heat only, see below     */
+    int32_t boundary; /* SWEPT_BC_*: periodic (0) or walls, see below         */
     double boundary_value; /* SWEPT_BC_DIRICHLET: the fixed ghost-cell value   */
 } swept_problem;
 
@@ -90,11 +90,18 @@ typedef struct {
  * its periodic ones, so the same shapes and phases apply unchanged.  The
  * heat adjoint takes the walls too (the walled step is affine: lambda runs
  * its homogeneous part, and dJ/dalpha pairs with the walled Laplacian
- * including the ghosts), and so does the batch.  Euler takes
- * SWEPT_BC_PERIODIC only (SWEPT_ENOTSUP). */
+ * including the ghosts), and so does the batch.
+ * Euler takes SWEPT_BC_NEUMANN (zero gradient: the two ghost cells beyond an
+ * edge hold the edge cell) and SWEPT_BC_REFLECT (slip wall: ghost cell k
+ * beyond the edge holds the k-th cell inside, mirrored, with its momentum
+ * normal to the wall negated); a face's four-cell run reads ghosts from its
+ * own side, so each wall face exists once per side.  SWEPT_BC_DIRICHLET is
+ * SWEPT_ENOTSUP for Euler, SWEPT_BC_REFLECT is SWEPT_EINVAL for heat, and
+ * the batch runs Euler periodic only (SWEPT_ENOTSUP). */
 #define SWEPT_BC_PERIODIC 0
 #define SWEPT_BC_DIRICHLET 1
 #define SWEPT_BC_NEUMANN 2
+#define SWEPT_BC_REFLECT 3
 
 /* Euler scheme variants (App. B prints the limiter and the spectral radius
  * ambiguously).  0: pressure-ratio minmod face states, Q_L = Q_i +

@@ -76,6 +76,7 @@ def _declare(L):
         getattr(L, "oracle_l2_mismatch" + s).argtypes = [_P, _P, _I]
         getattr(L, "oracle_l2_mismatch" + s).restype = _D
         getattr(L, "oracle_euler_run" + s).argtypes = [_P, _P, _I, _D, _D, _D, _D, _I, _I]
+        getattr(L, "oracle_euler_run_bc" + s).argtypes = [_P, _P, _I, _D, _D, _D, _D, _I, _I, _I]
         getattr(L, "oracle_euler_work_values" + s).argtypes = [_I]
         getattr(L, "oracle_euler_work_values" + s).restype = _I
         getattr(L, "oracle_cfl_dt" + s).argtypes = [_P, _I, _D, _D, _D, _D]
@@ -98,7 +99,7 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p)
 
 
-BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2  # heat boundaries (see oracle.c)
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN, BC_REFLECT = 0, 1, 2, 3  # boundaries (see oracle.c)
 
 
 def heat_step(T: np.ndarray, r: float, bc: int = BC_PERIODIC, bcv: float = 0.0) -> np.ndarray:
@@ -155,15 +156,16 @@ LIMITER_LITERAL, SPEED_ROE = 1, 2  # scheme variant bits (see oracle.c)
 
 
 def euler_run(Q0: np.ndarray, dt: float, dx: float, dy: float, gamma: float, steps: int,
-              scheme: int = 0) -> np.ndarray:
-    """``steps`` RK2 steps of the 2D Euler equations; Q0 is (4, N, N); scheme = variant bits."""
+              scheme: int = 0, bc: int = 0) -> np.ndarray:
+    """``steps`` RK2 steps of the 2D Euler equations; Q0 is (4, N, N); scheme = variant bits;
+    bc = BC_PERIODIC, BC_NEUMANN (zero gradient) or BC_REFLECT (slip walls)."""
     Q = np.array(Q0, copy=True, order="C")
     N = Q.shape[1]
     s = _sfx(Q)
     nwork = getattr(lib(), "oracle_euler_work_values" + s)(N)
     work = np.empty(nwork, dtype=Q.dtype)
-    getattr(lib(), "oracle_euler_run" + s)(_ptr(Q), _ptr(work), N, float(dt), float(dx), float(dy),
-                                           float(gamma), int(steps), int(scheme))
+    getattr(lib(), "oracle_euler_run_bc" + s)(_ptr(Q), _ptr(work), N, float(dt), float(dx), float(dy),
+                                              float(gamma), int(steps), int(scheme), int(bc))
     return Q
 
 

@@ -97,17 +97,15 @@ def _roe_speed(L, R, a, gm1):
     return np.abs(ua) + np.sqrt(gm1 * (H - t(0.5) * (ua * ua + ub * ub)))
 
 
-def _face_flux(Q, axis, gamma, scheme=0):
-    """Flux through the face between each cell and its +axis neighbour (scheme: variant bits,
-    1 = limiter exponents as printed, 2 = spectral radius at the Roe average)."""
-    t = Q.dtype.type
+def _run_flux(A, B, C, D, a, gamma, scheme):
+    """Numerical flux through the face between B and C of the runs A, B, C, D (arrays of
+    conserved states, elementwise): pressure-ratio reconstruction, then the Rusanov form
+    (scheme: variant bits, 1 = limiter exponents as printed, 2 = Roe-averaged speed)."""
+    t = B.dtype.type
     gm1 = gamma - t(1)
-    a = 1 if axis == "x" else 2
-    shift = (lambda A, k: _sh(A, k, 0)) if axis == "x" else (lambda A, k: _sh(A, 0, k))
-    p = _pressure(Q, gm1)
+    pA, pB, pC, pD = (_pressure(X, gm1) for X in (A, B, C, D))
     with np.errstate(divide="ignore", invalid="ignore"):
-        # face between B (this cell) and C (its +axis neighbour): 1/r_B and r_C through 1/(pC - pB)
-        pA, pB, pC, pD = shift(p, -1), p, shift(p, 1), shift(p, 2)
+        # 1/r_B and r_C through the shared 1/(pC - pB)
         inv_d = t(1) / (pC - pB)
         iB = (pB - pA) * inv_d
         rC = (pD - pC) * inv_d
@@ -119,31 +117,68 @@ def _face_flux(Q, axis, gamma, scheme=0):
         else:
             phiL = t(0.5) * np.minimum(iB, t(1))
             phiR = t(0.5) * np.minimum(rC, t(1))
-    B = Q
-    C = shift(Q, 1)
-    L = np.where(okB[None], B + phiL[None] * (C - B), B)
-    R = np.where(okC[None], C + phiR[None] * (B - C), C)
+        L = np.where(okB[None], B + phiL[None] * (C - B), B)
+        R = np.where(okC[None], C + phiR[None] * (B - C), C)
     fL, sL = _phys_flux(L, a, gamma, gm1)
     fR, sR = _phys_flux(R, a, gamma, gm1)
     s = _roe_speed(L, R, a, gm1) if scheme & 2 else np.maximum(sL, sR)
     return t(0.5) * ((fR + fL) + s[None] * (L - R))
 
 
-def euler_stage(Qbase, Qflux, hx, hy, gamma, scheme=0):
-    fx = _face_flux(Qflux, "x", gamma, scheme)
-    gy = _face_flux(Qflux, "y", gamma, scheme)
-    dF = fx - _sh(fx, -1, 0)
-    dG = gy - _sh(gy, 0, -1)
+def _face_flux(Q, axis, gamma, scheme=0):
+    """Flux through the face between each cell and its +axis neighbour (periodic)."""
+    a = 1 if axis == "x" else 2
+    shift = (lambda A, k: _sh(A, k, 0)) if axis == "x" else (lambda A, k: _sh(A, 0, k))
+    return _run_flux(shift(Q, -1), Q, shift(Q, 1), shift(Q, 2), a, gamma, scheme)
+
+
+def _wall_faces(Q, axis, gamma, scheme, bc):
+    """The N + 1 faces along axis (face f between cells f - 1 and f; faces 0 and N are the
+    walls) with two ghost cells per side: the edge cell (bc 2, zero gradient) or the mirrored
+    cells with the normal momentum negated (bc 3, slip wall)."""
+    a = 1 if axis == "x" else 2
+    ax = -1 if axis == "x" else -2
+    width = [(0, 0)] * Q.ndim
+    width[ax] = (2, 2)
+    P = np.pad(Q, width, mode="edge" if bc == 2 else "symmetric")
+    if bc == 3:
+        n = Q.shape[ax]
+        idx = [slice(None)] * Q.ndim
+        for sl in (slice(0, 2), slice(n + 2, n + 4)):
+            idx[0] = a
+            idx[ax] = sl
+            P[tuple(idx)] = -P[tuple(idx)]
+    n = Q.shape[ax]
+
+    def cut(k):
+        idx = [slice(None)] * Q.ndim
+        idx[ax] = slice(k, k + n + 1)
+        return P[tuple(idx)]
+
+    return _run_flux(cut(0), cut(1), cut(2), cut(3), a, gamma, scheme)
+
+
+def euler_stage(Qbase, Qflux, hx, hy, gamma, scheme=0, bc=0):
+    if bc == 0:
+        fx = _face_flux(Qflux, "x", gamma, scheme)
+        gy = _face_flux(Qflux, "y", gamma, scheme)
+        dF = fx - _sh(fx, -1, 0)
+        dG = gy - _sh(gy, 0, -1)
+    else:
+        fx = _wall_faces(Qflux, "x", gamma, scheme, bc)
+        gy = _wall_faces(Qflux, "y", gamma, scheme, bc)
+        dF = fx[..., 1:] - fx[..., :-1]
+        dG = gy[..., 1:, :] - gy[..., :-1, :]
     return (Qbase - hx * dF) - hy * dG
 
 
-def euler_run(Q0, dt, dx, dy, gamma, steps, scheme=0):
+def euler_run(Q0, dt, dx, dy, gamma, steps, scheme=0, bc=0):
     Q = np.array(Q0, copy=True)
     t = Q.dtype.type
     g = t(gamma)
     hx, hy = t(0.5 * dt / dx), t(0.5 * dt / dy)
     kx, ky = t(dt / dx), t(dt / dy)
     for _ in range(steps):
-        Qs = euler_stage(Q, Q, hx, hy, g, scheme)
-        Q = euler_stage(Q, Qs, kx, ky, g, scheme)
+        Qs = euler_stage(Q, Q, hx, hy, g, scheme, bc)
+        Q = euler_stage(Q, Qs, kx, ky, g, scheme, bc)
     return Q

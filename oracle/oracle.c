@@ -74,6 +74,7 @@ static inline int64_t wrap(int64_t i, int64_t n) { return (i % n + n) % n; }
 #define BC_PERIODIC 0
 #define BC_DIRICHLET 1
 #define BC_NEUMANN 2
+#define BC_REFLECT 3 /* Euler slip wall, see euler_ghost */
 
 /* Value of neighbour (i, j) of cell (ci, cj), which may lie outside the
  * square by one cell. */
@@ -405,30 +406,103 @@ static void euler_stage(const REAL* Qbase, const REAL* Qflux, REAL* Qout, int64_
     }
 }
 
+/* Euler walls.  With walls a row has N + 1 faces, f = 0 .. N (face f lies
+ * between cells f - 1 and f; faces 0 and N are the two walls), and each face
+ * reads the cells f - 2 .. f + 1, where cells outside [0, N) are ghosts:
+ *   BC_NEUMANN (zero gradient, transmissive): a ghost holds the edge cell;
+ *   BC_REFLECT (slip wall): ghost -1 - k holds cell k (ghost N + k holds
+ *     cell N - 1 - k) with the momentum normal to the wall negated.
+ * k is the cell index along the face normal, a the normal momentum (1: x,
+ * 2: y); (i, j) the cell's other coordinates are given by the caller. */
+static inline state4 euler_ghost(const REAL* Q, int64_t NN, int64_t N, int64_t k, int64_t other, int a, int bc)
+{
+    int64_t kk = k;
+    int flip = 0;
+    if (k < 0 || k >= N) {
+        if (bc == BC_NEUMANN) {
+            kk = k < 0 ? 0 : N - 1;
+        } else {
+            kk = k < 0 ? -1 - k : 2 * N - 1 - k;
+            flip = 1;
+        }
+    }
+    state4 s = load4(Q, NN, a == 1 ? other * N + kk : kk * N + other);
+    if (flip) s.v[a] = -s.v[a];
+    return s;
+}
+
+/* One RK stage with walls: faces 0 .. N per row (x) and per column (y),
+ * Qout = Qbase - hx (F_{i+1} - F_i) - hy (G_{j+1} - G_j) with face i left
+ * of cell i.  fx and gy hold 4*N*(N+1) values each. */
+static void euler_stage_walls(const REAL* Qbase, const REAL* Qflux, REAL* Qout, int64_t N, REAL hx, REAL hy,
+                              REAL gamma, int scheme, int bc, REAL* fx, REAL* gy)
+{
+    const int64_t NN = N * N, NF = N * (N + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+        for (int64_t f = 0; f <= N; ++f) {
+            REAL o[4];
+            /* x face f of row j: cells f-2 .. f+1 */
+            face_flux(euler_ghost(Qflux, NN, N, f - 2, j, 1, bc), euler_ghost(Qflux, NN, N, f - 1, j, 1, bc),
+                      euler_ghost(Qflux, NN, N, f, j, 1, bc), euler_ghost(Qflux, NN, N, f + 1, j, 1, bc), 1, gamma,
+                      scheme, o);
+            for (int c = 0; c < 4; ++c) fx[c * NF + j * (N + 1) + f] = o[c];
+            /* y face f of column j */
+            face_flux(euler_ghost(Qflux, NN, N, f - 2, j, 2, bc), euler_ghost(Qflux, NN, N, f - 1, j, 2, bc),
+                      euler_ghost(Qflux, NN, N, f, j, 2, bc), euler_ghost(Qflux, NN, N, f + 1, j, 2, bc), 2, gamma,
+                      scheme, o);
+            for (int c = 0; c < 4; ++c) gy[c * NF + j * (N + 1) + f] = o[c];
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t j = 0; j < N; ++j) {
+        for (int64_t i = 0; i < N; ++i) {
+            const int64_t k = j * N + i;
+            for (int c = 0; c < 4; ++c) {
+                const REAL dF = fx[c * NF + j * (N + 1) + i + 1] - fx[c * NF + j * (N + 1) + i];
+                const REAL dG = gy[c * NF + i * (N + 1) + j + 1] - gy[c * NF + i * (N + 1) + j];
+                Qout[c * NN + k] = (Qbase[c * NN + k] - hx * dF) - hy * dG;
+            }
+        }
+    }
+}
+
 /* M explicit-midpoint RK2 steps of the 2D Euler equations on an N x N
  * periodic grid with spacings dx, dy.  Q (4*N*N) holds Q^0 on entry and
  * Q^M on exit; work must hold 16*N*N values (Q*, Q^{n+1}, face fluxes);
  * scheme = variant bits (0: minmod + Rusanov). */
-void NAME(oracle_euler_run)(REAL* Q, REAL* work, int64_t N, double dt, double dx, double dy, double gamma_in,
-                            int64_t M, int64_t scheme)
+void NAME(oracle_euler_run_bc)(REAL* Q, REAL* work, int64_t N, double dt, double dx, double dy, double gamma_in,
+                               int64_t M, int64_t scheme, int64_t bc)
 {
-    const int64_t NN = N * N;
+    const int64_t NN = N * N, NF = N * (N + 1);
     REAL* qs = work;
     REAL* qn = work + 4 * NN;
     REAL* fx = work + 8 * NN;
-    REAL* gy = work + 12 * NN;
+    REAL* gy = fx + 4 * NF;
     const REAL gamma = (REAL)gamma_in;
     const REAL hx = (REAL)(0.5 * dt / dx), hy = (REAL)(0.5 * dt / dy);
     const REAL kx = (REAL)(dt / dx), ky = (REAL)(dt / dy);
     for (int64_t m = 0; m < M; ++m) {
-        euler_stage(Q, Q, qs, N, hx, hy, gamma, (int)scheme, fx, gy);
-        euler_stage(Q, qs, qn, N, kx, ky, gamma, (int)scheme, fx, gy);
+        if (bc == BC_PERIODIC) {
+            euler_stage(Q, Q, qs, N, hx, hy, gamma, (int)scheme, fx, gy);
+            euler_stage(Q, qs, qn, N, kx, ky, gamma, (int)scheme, fx, gy);
+        } else {
+            euler_stage_walls(Q, Q, qs, N, hx, hy, gamma, (int)scheme, (int)bc, fx, gy);
+            euler_stage_walls(Q, qs, qn, N, kx, ky, gamma, (int)scheme, (int)bc, fx, gy);
+        }
         memcpy(Q, qn, (size_t)(4 * NN) * sizeof(REAL));
     }
 }
 
-/* Work size, in values, that oracle_euler_run needs. */
-int64_t NAME(oracle_euler_work_values)(int64_t N) { return 16 * N * N; }
+/* Periodic run. */
+void NAME(oracle_euler_run)(REAL* Q, REAL* work, int64_t N, double dt, double dx, double dy, double gamma_in,
+                            int64_t M, int64_t scheme)
+{
+    NAME(oracle_euler_run_bc)(Q, work, N, dt, dx, dy, gamma_in, M, scheme, BC_PERIODIC);
+}
+
+/* Work size, in values, that oracle_euler_run(_bc) needs. */
+int64_t NAME(oracle_euler_work_values)(int64_t N) { return 16 * N * N + 8 * N; }
 
 /* Stable time step for a CFL number: dt = cfl / max_cells((|u|+c)/dx + (|v|+c)/dy),
  * evaluated in double from the (exactly widened) state.  Not in the paper,

@@ -21,7 +21,7 @@ CODES = {v: k for k, v in ERRORS.items()}
 HEAT, EULER = 0, 1
 F64, F32 = 0, 1
 LIMITER_LITERAL, SPEED_ROE = 1, 2  # Euler scheme variant bits (swept.h)
-BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN = 0, 1, 2  # boundaries (swept.h; heat only for the last two)
+BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN, BC_REFLECT = 0, 1, 2, 3  # boundaries (swept.h)
 
 
 class SweptError(RuntimeError):

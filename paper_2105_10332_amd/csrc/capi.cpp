@@ -85,10 +85,12 @@ int derive(const swept_problem* p, const swept_tuning* t, Derived* d)
     if (!(p->lx > 0) || !(p->ly > 0) || !std::isfinite(p->lx) || !std::isfinite(p->ly))
         return fail(SWEPT_EINVAL, "domain lengths must be positive");
     if (!(p->dt > 0) || !std::isfinite(p->dt)) return fail(SWEPT_EUNSTABLE, "dt must be positive (dt=%g)", p->dt);
-    if (p->boundary < SWEPT_BC_PERIODIC || p->boundary > SWEPT_BC_NEUMANN)
+    if (p->boundary < SWEPT_BC_PERIODIC || p->boundary > SWEPT_BC_REFLECT)
         return fail(SWEPT_EINVAL, "unknown boundary %d", p->boundary);
-    if (p->boundary != SWEPT_BC_PERIODIC && p->kind != SWEPT_HEAT)
-        return fail(SWEPT_ENOTSUP, "Euler is periodic only");
+    if (p->kind == SWEPT_HEAT && p->boundary == SWEPT_BC_REFLECT)
+        return fail(SWEPT_EINVAL, "heat has no slip wall (use SWEPT_BC_NEUMANN)");
+    if (p->kind == SWEPT_EULER && p->boundary == SWEPT_BC_DIRICHLET)
+        return fail(SWEPT_ENOTSUP, "Euler walls are SWEPT_BC_NEUMANN (zero gradient) or SWEPT_BC_REFLECT");
     if (!std::isfinite(p->boundary_value)) return fail(SWEPT_EINVAL, "boundary value must be finite");
     if (p->scheme & ~(SWEPT_LIMITER_LITERAL | SWEPT_SPEED_ROE))
         return fail(SWEPT_EINVAL, "unknown scheme bits %d", p->scheme);
@@ -280,7 +282,9 @@ int swept_init(swept_ctx** ctx, const swept_problem* prob, const swept_tuning* t
         c->c[4] = prob->dt / d.dy;
     }
     // fused Euler step tile: the largest of 16, 8, 4 dividing nx (nx is a multiple of 4 for Euler)
-    c->std_ts = (prob->nx % 16 == 0) ? 16 : (prob->nx % 8 == 0) ? 8 : 4;
+    // whose window (tile + 4-cell halo) is at most nx wide, so a window meets the domain edge at
+    // most once (the walls substitute ghost cells at that one edge)
+    c->std_ts = (prob->nx % 16 == 0 && prob->nx >= 24) ? 16 : (prob->nx % 8 == 0 && prob->nx >= 16) ? 8 : 4;
     c->tab_dev = reinterpret_cast<swept::LevelEntry*>(w + align_up(d.state_bytes) +
                                                       align_up(sizeof(double) * 4 * kParts) +
                                                       align_up(sizeof(double) * 4));
@@ -541,6 +545,7 @@ int standard_advance(swept_ctx* c, int64_t n_steps)
             a.N = c->prob.nx;
             a.ts = c->std_ts;
             a.scheme = c->prob.scheme;
+            a.bc = c->prob.boundary;
             for (int k = 0; k < 5; ++k) a.p[k] = c->c[k];
             e = swept::launch_euler_standard(c->prob.dtype, in, out, a, c->stream);
         }
@@ -638,6 +643,8 @@ int batch_derive(const swept_problem* probs, const swept_tuning* tunes, int32_t 
     size_t off = 0;
     for (int q = 0; q < count; ++q) {
         if (probs[q].dtype != probs[0].dtype) return fail(SWEPT_EINVAL, "all problems of a batch share one dtype");
+        if (probs[q].kind == SWEPT_EULER && probs[q].boundary != SWEPT_BC_PERIODIC)
+            return fail(SWEPT_ENOTSUP, "problem %d: the batch runs Euler periodic only", q);
         swept_tuning t{tunes ? tunes[q].tile : 0, swept::batch_wg(probs[0].dtype)};
         const int rc = derive(&probs[q], &t, &(*d)[q]);
         if (rc) return rc;

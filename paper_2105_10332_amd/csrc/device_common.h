@@ -32,11 +32,60 @@ struct HeatSV {
 using HeatS = HeatSV<0>;
 // Euler with scheme variant V (limiter and spectral-radius bits, scheme.h);
 // register-heavy per-cell update: at most 512 threads (FP32) or 256 (FP64)
-template <int V>
+template <int V, int BC = 0>
 struct EulerSV {
-    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 512, SCHEME = V, BOUNDARY = 0;
+    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 512, SCHEME = V, BOUNDARY = BC;
 };
 using EulerS = EulerSV<0>;
+
+// Euler walls.  A face's run of four cells that reaches across the domain
+// edge reads ghost cells from its own side of the edge instead of the
+// wrapped cells: BC 2 (zero gradient) the edge cell, BC 3 (slip wall) the
+// cell mirrored across the edge with its normal momentum negated.  E is the
+// window-local index of the first cell past the edge (global index 0) along
+// the face normal; `left` says the face belongs to the cells below E.
+// Returns the window-local index to read for run cell m; flip = negate the
+// normal momentum.  The returned index lies inside the run's own range.
+template <int BC>
+__device__ __forceinline__ int wall_cell(int m, int E, bool left, bool& flip)
+{
+    flip = false;
+    if (left ? m < E : m >= E) return m;
+    if constexpr (BC == 3) {
+        flip = true;
+        return 2 * E - 1 - m;
+    }
+    return left ? E - 1 : E;
+}
+
+// Window-local index of the domain's first column (row) in a window whose
+// cell 0 is at global o and which holds W cells, or a sentinel far below 0
+// when the window does not reach the edge.
+__device__ __forceinline__ int window_edge(int o, int W, int N)
+{
+    return o < 0 ? -o : (o + W > N ? N - o : -(1 << 20));
+}
+
+// Numerical flux through the face after window-local cell a (A = 1: x, the
+// run a-1 .. a+2 along a row starting at row offset `base`; A = 2: y, the run
+// along a column, `base` the column) with the walls' ghost cells.
+template <typename T, int A, int V, int BC>
+__device__ __forceinline__ void wall_face(const T* __restrict__ prev, const T* __restrict__ pbuf, int W, int P,
+                                          int base, int a, int E, bool left, T gamma, T out[4])
+{
+    T q[4][4], p[4];
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+        bool flip;
+        const int m = wall_cell<BC>(a - 1 + o, E, left, flip);
+        const int li = A == 1 ? base + m : m * W + base;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) q[o][c] = prev[c * P + li];
+        if (flip) q[o][A] = -q[o][A];
+        p[o] = pbuf[li];
+    }
+    face_flux<T, A, V>(q[0], q[1], q[2], q[3], p[0], p[1], p[2], p[3], gamma, out);
+}
 
 __device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
 {
@@ -184,10 +233,15 @@ __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>&
     }
 }
 
-template <typename T, int V, class Store>
+// BC != 0: walls (see wall_cell); ex, ey are the window-local indices of the
+// domain's first column and row (window_edge).  A face at the edge itself
+// exists once per side: the face buffer keeps the lower side's flux, and the
+// first cell past the edge recomputes its own.
+template <typename T, int V, class Store, int BC = 0>
 __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, T* __restrict__ pbuf,
                                             T* __restrict__ fbuf, int FS, int W, int P, int x0, int y0, int fw, int fh,
-                                            bool second_stage, T gamma, T cx, T cy, const Store& store)
+                                            bool second_stage, T gamma, T cx, T cy, const Store& store, int ex = 0,
+                                            int ey = 0)
 {
     const int nthr = blockDim.x, tid = threadIdx.x;
     const T gm1 = gamma - T(1);
@@ -212,14 +266,19 @@ __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, 
             const int k = i - q * nf;
             const int lb = (y0 + q) * W + (x0 - 1 + k);
             T qa[4], qb[4], qc[4], qd[4], f[4];
+            const int a = x0 - 1 + k;
+            if (BC != 0 && a - 1 < ex && a + 2 >= ex) {
+                wall_face<T, 1, V, BC>(prev, pbuf, W, P, (y0 + q) * W, a, ex, a < ex, gamma, f);
+            } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                qa[c] = prev[c * P + lb - 1];
-                qb[c] = prev[c * P + lb];
-                qc[c] = prev[c * P + lb + 1];
-                qd[c] = prev[c * P + lb + 2];
+                for (int c = 0; c < 4; ++c) {
+                    qa[c] = prev[c * P + lb - 1];
+                    qb[c] = prev[c * P + lb];
+                    qc[c] = prev[c * P + lb + 1];
+                    qd[c] = prev[c * P + lb + 2];
+                }
+                face_flux<T, 1, V>(qa, qb, qc, qd, pbuf[lb - 1], pbuf[lb], pbuf[lb + 1], pbuf[lb + 2], gamma, f);
             }
-            face_flux<T, 1, V>(qa, qb, qc, qd, pbuf[lb - 1], pbuf[lb], pbuf[lb + 1], pbuf[lb + 2], gamma, f);
 #pragma unroll
             for (int c = 0; c < 4; ++c) fbuf[c * FS + i] = f[c];
         }
@@ -234,10 +293,15 @@ __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, 
             const int k = i - q * fw;
             const int li = (y0 + q) * W + (x0 + k);
             const int fi = q * nf + k;  // face i-1/2; face i+1/2 is fi + 1
+            T fl[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fl[c] = fbuf[c * FS + fi];
+            if (BC != 0 && x0 + k == ex)  // the wall face as seen from this side
+                wall_face<T, 1, V, BC>(prev, pbuf, W, P, (y0 + q) * W, ex - 1, ex, false, gamma, fl);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 const T base = second_stage ? cur[c * P + li] : prev[c * P + li];
-                const T dF = fbuf[c * FS + fi + 1] - fbuf[c * FS + fi];
+                const T dF = fbuf[c * FS + fi + 1] - fl[c];
                 cur[c * P + li] = base - cx * dF;
             }
         }
@@ -250,14 +314,20 @@ __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, 
             const int xo = i - k * fw;
             const int lb = (y0 - 1 + k) * W + (x0 + xo);
             T qa[4], qb[4], qc[4], qd[4], f[4];
+            const int a = y0 - 1 + k;
+            if (BC != 0 && a - 1 < ey && a + 2 >= ey) {
+                wall_face<T, 2, V, BC>(prev, pbuf, W, P, x0 + xo, a, ey, a < ey, gamma, f);
+            } else {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                qa[c] = prev[c * P + lb - W];
-                qb[c] = prev[c * P + lb];
-                qc[c] = prev[c * P + lb + W];
-                qd[c] = prev[c * P + lb + 2 * W];
+                for (int c = 0; c < 4; ++c) {
+                    qa[c] = prev[c * P + lb - W];
+                    qb[c] = prev[c * P + lb];
+                    qc[c] = prev[c * P + lb + W];
+                    qd[c] = prev[c * P + lb + 2 * W];
+                }
+                face_flux<T, 2, V>(qa, qb, qc, qd, pbuf[lb - W], pbuf[lb], pbuf[lb + W], pbuf[lb + 2 * W], gamma,
+                                   f);
             }
-            face_flux<T, 2, V>(qa, qb, qc, qd, pbuf[lb - W], pbuf[lb], pbuf[lb + W], pbuf[lb + 2 * W], gamma, f);
 #pragma unroll
             for (int c = 0; c < 4; ++c) fbuf[c * FS + i] = f[c];
         }
@@ -270,10 +340,14 @@ __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, 
             const int lx = x0 + k, ly = y0 + q;
             const int li = ly * W + lx;
             const int fi = q * fw + k;  // face j-1/2; face j+1/2 is fi + fw
-            T out[4];
+            T fl[4], out[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) fl[c] = fbuf[c * FS + fi];
+            if (BC != 0 && ly == ey)  // the wall face as seen from this side
+                wall_face<T, 2, V, BC>(prev, pbuf, W, P, lx, ey - 1, ey, false, gamma, fl);
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const T dG = fbuf[c * FS + fi + fw] - fbuf[c * FS + fi];
+                const T dG = fbuf[c * FS + fi + fw] - fl[c];
                 out[c] = cur[c * P + li] - cy * dG;
                 cur[c * P + li] = out[c];
             }
@@ -485,8 +559,15 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
             const int FS = (b + 1) * b;
             const bool second = (lvl & 1) == 0;
             const SweptStore<T, NVAR> st{gout, NN, N, ox, oy, C, hx2, hy2};
-            euler_level<T, S::SCHEME>(prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second, (T)a.p[0],
-                                      (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]), st);
+            if (S::BOUNDARY != 0 && wraps)
+                euler_level<T, S::SCHEME, SweptStore<T, NVAR>, S::BOUNDARY>(
+                    prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second, (T)a.p[0],
+                    (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]), st, window_edge(ox, W, N),
+                    window_edge(oy, W, N));
+            else
+                euler_level<T, S::SCHEME>(prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second,
+                                          (T)a.p[0], (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]),
+                                          st);
         }
         __syncthreads();
     }

@@ -89,7 +89,7 @@ struct TileStore {
     }
 };
 
-template <typename T, int V>
+template <typename T, int V, int BC>
 __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict__ in, T* __restrict__ out,
                                                              StdArgs a)
 {
@@ -112,11 +112,20 @@ __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict
     T* pbuf = lds + 2 * BUF;
     T* fbuf = pbuf + P;
     const T gamma = (T)a.p[0];
-    euler_level<T, V>(q0, q1, pbuf, fbuf, FS, W, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1], (T)a.p[2],
-                      NoStore{});
-    __syncthreads();
     const TileStore<T> st{out, NN, N, tx0 - 4, ty0 - 4};
-    euler_level<T, V>(q1, q0, pbuf, fbuf, FS, W, P, 4, 4, TS, TS, true, gamma, (T)a.p[3], (T)a.p[4], st);
+    const int ex = window_edge(tx0 - 4, W, N), ey = window_edge(ty0 - 4, W, N);
+    if (BC != 0 && (ex >= 0 || ey >= 0)) {  // a tile at the walls
+        euler_level<T, V, NoStore, BC>(q0, q1, pbuf, fbuf, FS, W, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1],
+                                       (T)a.p[2], NoStore{}, ex, ey);
+        __syncthreads();
+        euler_level<T, V, TileStore<T>, BC>(q1, q0, pbuf, fbuf, FS, W, P, 4, 4, TS, TS, true, gamma, (T)a.p[3],
+                                            (T)a.p[4], st, ex, ey);
+    } else {
+        euler_level<T, V>(q0, q1, pbuf, fbuf, FS, W, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1], (T)a.p[2],
+                          NoStore{});
+        __syncthreads();
+        euler_level<T, V>(q1, q0, pbuf, fbuf, FS, W, P, 4, 4, TS, TS, true, gamma, (T)a.p[3], (T)a.p[4], st);
+    }
 }
 
 // --------------------------------------------------------------- reductions
@@ -218,10 +227,18 @@ static const void* phase_kernel(int tile)
     return (const void*)swept_phase_kernel<S, T, 0>;
 }
 
-template <int V>
-static const void* euler_phase_kernel(int dtype)
+template <int V, int BC>
+static const void* euler_phase_v(int dtype)
 {
-    return dtype == 0 ? phase_kernel<EulerSV<V>, double>(0) : phase_kernel<EulerSV<V>, float>(0);
+    return dtype == 0 ? phase_kernel<EulerSV<V, BC>, double>(0) : phase_kernel<EulerSV<V, BC>, float>(0);
+}
+
+template <int V>
+static const void* euler_phase_kernel(int dtype, int bc)
+{
+    if (bc == 2) return euler_phase_v<V, 2>(dtype);
+    if (bc == 3) return euler_phase_v<V, 3>(dtype);
+    return euler_phase_v<V, 0>(dtype);
 }
 
 template <int BC>
@@ -240,10 +257,10 @@ static const void* phase_kernel(int kind, int dtype, int tile, int scheme, int b
         return heat_phase_kernel<0>(dtype, tile);
     }
     switch (scheme) {
-        case 1: return euler_phase_kernel<1>(dtype);
-        case 2: return euler_phase_kernel<2>(dtype);
-        case 3: return euler_phase_kernel<3>(dtype);
-        default: return euler_phase_kernel<0>(dtype);
+        case 1: return euler_phase_kernel<1>(dtype, bc);
+        case 2: return euler_phase_kernel<2>(dtype, bc);
+        case 3: return euler_phase_kernel<3>(dtype, bc);
+        default: return euler_phase_kernel<0>(dtype, bc);
     }
 }
 
@@ -258,11 +275,12 @@ hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t 
 hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds)
 {
     hipError_t e = hipSuccess;
-    for (int v = 0; v < (kind == 0 ? 3 : 4); ++v)  // heat: boundaries; Euler: scheme bits
-        for (int tile : {0, 16, 32, 64})
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile, kind == 0 ? 0 : v, kind == 0 ? v : 0),
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    for (int bc = 0; bc < 4; ++bc)  // heat: boundaries 0-2; Euler: boundaries 0, 2, 3 x scheme bits
+        for (int v = 0; v < (kind == 0 ? 1 : 4); ++v)
+            for (int tile : {0, 16, 32, 64})
+                if (e == hipSuccess && !(kind == 0 && bc == 3) && !(kind == 1 && bc == 1))
+                    e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile, v, bc),
+                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return e;
 }
 
@@ -300,27 +318,38 @@ size_t euler_phase_lds(int dtype, int tile)
     return s * euler_lds_values(tile + 4, (tile + 1) * tile);
 }
 
-template <int V>
-static const void* euler_standard_v(int dtype)
+template <int V, int BC>
+static const void* euler_standard_vb(int dtype)
 {
-    return dtype == 0 ? (const void*)euler_standard_kernel<double, V> : (const void*)euler_standard_kernel<float, V>;
+    return dtype == 0 ? (const void*)euler_standard_kernel<double, V, BC>
+                      : (const void*)euler_standard_kernel<float, V, BC>;
 }
 
-static const void* euler_standard(int dtype, int scheme)
+template <int V>
+static const void* euler_standard_v(int dtype, int bc)
+{
+    if (bc == 2) return euler_standard_vb<V, 2>(dtype);
+    if (bc == 3) return euler_standard_vb<V, 3>(dtype);
+    return euler_standard_vb<V, 0>(dtype);
+}
+
+static const void* euler_standard(int dtype, int scheme, int bc)
 {
     switch (scheme) {
-        case 1: return euler_standard_v<1>(dtype);
-        case 2: return euler_standard_v<2>(dtype);
-        case 3: return euler_standard_v<3>(dtype);
-        default: return euler_standard_v<0>(dtype);
+        case 1: return euler_standard_v<1>(dtype, bc);
+        case 2: return euler_standard_v<2>(dtype, bc);
+        case 3: return euler_standard_v<3>(dtype, bc);
+        default: return euler_standard_v<0>(dtype, bc);
     }
 }
 
 hipError_t set_euler_standard_lds_limit(int dtype, size_t lds)
 {
     hipError_t e = hipSuccess;
-    for (int scheme = 0; scheme < 4 && e == hipSuccess; ++scheme)
-        e = hipFuncSetAttribute(euler_standard(dtype, scheme), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    for (int bc : {0, 2, 3})
+        for (int scheme = 0; scheme < 4 && e == hipSuccess; ++scheme)
+            e = hipFuncSetAttribute(euler_standard(dtype, scheme, bc), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds);
     return e;
 }
 
@@ -329,7 +358,7 @@ hipError_t launch_euler_standard(int dtype, const void* in, void* out, const Std
     dim3 grd(a.N / a.ts, a.N / a.ts);
     const size_t lds = euler_standard_lds(dtype, a.ts);
     void* args[] = {(void*)&in, (void*)&out, (void*)&a};
-    return hipLaunchKernel(euler_standard(dtype, a.scheme), grd, dim3(256), args, lds, st);
+    return hipLaunchKernel(euler_standard(dtype, a.scheme, a.bc), grd, dim3(256), args, lds, st);
 }
 
 hipError_t launch_plane_sums(int dtype, const void* x, int nvar, size_t NN, double* partials, int nparts,

@@ -60,6 +60,7 @@ struct StdArgs {
     int N;
     int ts;      // output tile edge of the fused Euler step
     int scheme;  // Euler scheme variant bits (scheme.h)
+    int bc;      // Euler walls: 0 periodic, 2 zero gradient, 3 slip
     double p[5];
 };
 

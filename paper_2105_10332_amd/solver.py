@@ -12,8 +12,8 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC, EULER, F32, F64, HEAT, LIMITER_LITERAL, SPEED_ROE, Info,
-                   Problem, Tuning, check, lib)
+from ._lib import (BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC, BC_REFLECT, EULER, F32, F64, HEAT, LIMITER_LITERAL,
+                   SPEED_ROE, Info, Problem, Tuning, check, lib)
 
 _DT = {torch.float64: F64, torch.float32: F32}
 
@@ -21,7 +21,8 @@ _DT = {torch.float64: F64, torch.float32: F32}
 def make_problem(kind: int, n: int, dtype: torch.dtype, dt: float, length: float, alpha: float = 1.0,
                  gamma: float = 1.4, scheme: int = 0, boundary: int = 0, boundary_value: float = 0.0) -> Problem:
     """scheme: Euler variant bits, LIMITER_LITERAL | SPEED_ROE (0 = minmod + Rusanov).
-    boundary: BC_PERIODIC, or for heat BC_DIRICHLET (ghost cells hold boundary_value) / BC_NEUMANN."""
+    boundary: BC_PERIODIC; heat BC_DIRICHLET (ghost cells hold boundary_value) or BC_NEUMANN (zero
+    flux); Euler BC_NEUMANN (zero gradient) or BC_REFLECT (slip walls)."""
     return Problem(kind, _DT[dtype], n, n, float(length), float(length), float(dt), float(alpha), float(gamma),
                    int(scheme), int(boundary), float(boundary_value))
 
@@ -228,4 +229,5 @@ def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 
 
 
 __all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT",
-           "EULER", "LIMITER_LITERAL", "SPEED_ROE", "BC_PERIODIC", "BC_DIRICHLET", "BC_NEUMANN", "_lib"]
+           "EULER", "LIMITER_LITERAL", "SPEED_ROE", "BC_PERIODIC", "BC_DIRICHLET", "BC_NEUMANN",
+           "BC_REFLECT", "_lib"]

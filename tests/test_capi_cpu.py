@@ -70,7 +70,9 @@ def test_workspace_size():
     (Problem(0, 0, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4, 1), 16, 0, "SWEPT_EINVAL"),    # heat has no variants
     (Problem(0, 0, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4, 0, 3), 16, 0, "SWEPT_EINVAL"),    # unknown boundary
     (Problem(0, 0, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4, 0, 1, float("nan")), 16, 0, "SWEPT_EINVAL"),  # NaN ghost
-    (Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 0, 2), 16, 0, "SWEPT_ENOTSUP"),  # Euler non-periodic
+    (Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 0, 1), 16, 0, "SWEPT_ENOTSUP"),  # Euler Dirichlet
+    (Problem(0, 0, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4, 0, 3), 16, 0, "SWEPT_EINVAL"),    # heat slip wall
+    (Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 0, 4), 16, 0, "SWEPT_EINVAL"),  # unknown boundary
 ])
 def test_validation_codes(prob, tile, wg, code):
     rc, _ = _ws(prob, tile, wg)
@@ -138,6 +140,10 @@ def test_batch_count_and_dtype_validation():
     assert L.swept_batch_workspace_bytes(variant, None, 2, ctypes.byref(out)) == 0  # variants batch too
     for scheme in (1, 2, 3):  # the single-problem path takes every variant
         assert _ws(Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, scheme), 16)[0] == 0
+    ewall = (Problem * 1)(Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 0, 3))
+    assert L.swept_batch_workspace_bytes(ewall, None, 1, ctypes.byref(out)) == CODES["SWEPT_ENOTSUP"]
+    for bc in (2, 3):  # the single-problem Euler path takes zero-gradient and slip walls
+        assert _ws(Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 0, bc), 16)[0] == 0
     walls = (Problem * 1)(Problem(0, 0, 32, 32, 1.0, 1.0, 1e-4, 1.0, 1.4, 0, 1, 0.5))
     assert L.swept_batch_workspace_bytes(walls, None, 1, ctypes.byref(out)) == 0  # walls batch too
     for bc in (1, 2):  # the single-problem heat path takes both

@@ -55,6 +55,42 @@ def test_scheme_variants_swept_equals_standard_and_oracle(scheme, dtype, tile, N
             assert rel_err(ref, oracle.euler_run(Q0, dt, 10.0 / N, 10.0 / N, GAMMA, steps)) > 1e-12
 
 
+@pytest.mark.parametrize("bc", [2, 3])
+@pytest.mark.parametrize("scheme", [0, 3])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("tile,N", [(8, 16), (8, 24), (16, 48), (32, 64), (12, 36)])
+def test_walls_swept_equals_standard_and_oracle(bc, scheme, dtype, tile, N):
+    """Zero-gradient (2) and slip (3) walls on the vortex: Swept == Standard bit for bit and
+    both equal the walled oracle (FP64 within 1e-10, FP32 within 1e-5)."""
+    Q0 = problems.shu_vortex(N)
+    dt = _dt(Q0, N)
+    Q0 = Q0.astype(dtype)
+    h = tile // 4
+    for steps in sorted({1, h + 1, 2 * h + 3, 9}):
+        sw = euler_gpu(Q0, dt, steps, tile, "swept", scheme=scheme, bc=bc)
+        st = euler_gpu(Q0, dt, steps, tile, "standard", scheme=scheme, bc=bc)
+        assert np.array_equal(sw, st), (bc, scheme, tile, N, steps)
+        ref = oracle.euler_run(Q0, dt, 10.0 / N, 10.0 / N, GAMMA, steps, scheme=scheme, bc=bc)
+        err = rel_err(sw, ref)
+        assert err <= (1e-10 if dtype == np.float64 else 1e-5), (err, steps)
+
+
+def test_slip_walls_conserve_mass_and_energy_on_gpu():
+    """128^2 vortex against slip walls, 60 steps: the FP64 sums of rho and E stay constant
+    to roundoff (a slip wall passes neither), the x momentum does not."""
+    Q0 = problems.shu_vortex(128)
+    dt = _dt(Q0, 128)
+    Q = torch.tensor(Q0, device=DEV)
+    s = SweptSolver(EULER, Q, dt=dt, length=10.0, gamma=GAMMA, tile=16, boundary=3)
+    s0 = np.array(s.swept_conserved())
+    s.swept_advance(60)
+    s1 = np.array(s.swept_conserved())
+    s.close()
+    scale = np.abs(Q0).reshape(4, -1).sum(axis=1)
+    assert abs(s1[0] - s0[0]) / scale[0] < 1e-12 and abs(s1[3] - s0[3]) / scale[3] < 1e-12
+    assert abs(s1[1] - s0[1]) / scale[1] > 1e-6
+
+
 def test_poisoned_workspace_and_determinism():
     Q0 = problems.shu_vortex(64)
     dt = _dt(Q0, 64)
