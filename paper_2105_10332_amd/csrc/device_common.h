@@ -463,9 +463,10 @@ constexpr int max_wg()
 template <class S, typename T, int B = 0>
 __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsigned char* smem_raw)
 {
-    // heat: windows that cross the domain edge first (-2.7% FP64, -3.6% FP32 on the
-    // 4096^2 advance); Euler keeps the row-major order (edge-first measured +1%)
-    constexpr bool ORDER_EDGE_FIRST = S::NVAR == 1;
+    // heat, and Euler with walls: windows that cross the domain edge first (heat -2.7% FP64,
+    // -3.6% FP32 on the 4096^2 advance; walled Euler windows at the edge recompute a wall
+    // face per row); periodic Euler keeps the row-major order (edge-first measured +1%)
+    constexpr bool ORDER_EDGE_FIRST = S::NVAR == 1 || S::BOUNDARY != 0;
     T* lds = reinterpret_cast<T*>(smem_raw);
     constexpr int NVAR = S::NVAR, R = S::R;
     const int b = B > 0 ? B : a.tile, h = B > 0 ? B / (2 * R) : a.h, N = a.N, L = a.L;
