@@ -17,7 +17,8 @@ Other workloads (--workload): euler (2048^2 vortex, 500 RK2 steps per
 step), adjoint (1024^2 FP32 heat, 2000 steps: forward with checkpoints +
 reverse sweep per step), batch (48 heat + 16 Euler problems, FP32, 200 steps,
 one persistent launch per step), study (the paper's parameter study at a
-GPU share of 100%: speedup over array sizes 320-1120 and block sizes 8-32).
+GPU share of 100%: speedup over array sizes 320-1120 and block sizes 8-32), graphs
+(eager launches against replayed HIP graphs at 320^2 and 1024^2).
 
 Usage: python bench.py [--steps K] [--warmup W] [--dtype f64|f32] [--tile B] [--workload W]
 """
@@ -76,7 +77,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["heat", "euler", "adjoint", "batch", "study"], default="heat")
+    ap.add_argument("--workload", choices=["heat", "euler", "adjoint", "batch", "study", "graphs"], default="heat")
     ap.add_argument("--dtype", choices=["f64", "f32"], default=None)
     ap.add_argument("--tile", type=int, default=0, help="0: tuned or default tile")
     ap.add_argument("--wg", type=int, default=0, help="0: tuned or library default")
@@ -482,6 +483,52 @@ def run_study(args):
     return out
 
 
+def run_graphs(args):
+    """Launch overhead at the paper's small array sizes: heat FP64, 500 steps, b = 32, each
+    advance issued eagerly (one call per launch) and replayed from a captured HIP graph,
+    for the swept and the Standard solver."""
+    import torch
+
+    from paper_2105_10332_amd import problems
+    from paper_2105_10332_amd.solver import HEAT, SweptSolver
+
+    M = args.advance_steps or 500
+    k = max(1, args.steps)
+    rows = {}
+    t_all = time.perf_counter()
+    for n in (320, 1024):
+        x = torch.tensor(problems.heat_fourier_modes(n), device="cuda")
+        s = SweptSolver(HEAT, x, dt=0.2 / n / n, length=1.0, alpha=1.0, tile=32, wg=512)
+        row = {}
+        for method in ("swept", "standard"):
+            fn = getattr(s, method + "_advance")
+            fn(M)
+            eager, _ = timed(lambda: fn(M), k)
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                fn(1)
+            torch.cuda.current_stream().wait_stream(side)
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn(M)
+            g.replay()
+            graph, _ = timed(g.replay, k)
+            row[method] = {"eager_ms": eager / k * 1e3, "graph_ms": graph / k * 1e3}
+        row["S_eager"] = row["standard"]["eager_ms"] / row["swept"]["eager_ms"]
+        row["S_graph"] = row["standard"]["graph_ms"] / row["swept"]["graph_ms"]
+        s.close()
+        rows[n] = row
+        print(f"graphs {n}: {row}", file=sys.stderr, flush=True)
+    cfg = {"workload": f"heat N x N FP64, N in (320, 1024), r=0.2, {M} steps, b=32 wg 512: each advance eager "
+                       f"and as a replayed HIP graph", "sizes": [320, 1024]}
+    out = base_record(args, rows[320]["S_graph"], "x (Standard / Swept time, both replayed from graphs, N=320)",
+                      time.perf_counter() - t_all, "f64", cfg)
+    out["ms_per_step"] = None
+    out["table"] = rows
+    return out
+
+
 def copy_reference(n: int = 4096, reps: int = 3):
     """A plain device-to-device copy of one n x n FP64 state, reps times: the known-size
     traffic that scales the HBM counters of the profiles."""
@@ -505,7 +552,7 @@ def main():
         copy_reference()
         return
     fn = {"heat": run_heat, "euler": run_euler, "adjoint": run_adjoint, "batch": run_batch,
-          "study": run_study}[args.workload]
+          "study": run_study, "graphs": run_graphs}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

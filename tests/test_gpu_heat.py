@@ -252,3 +252,38 @@ def test_nonfinite_state_is_reported():
         s.swept_conserved()
     assert ei.value.name == "SWEPT_ENONFINITE"
     s.close()
+
+
+@pytest.mark.parametrize("method", ["swept", "standard"])
+def test_advance_replays_from_a_hip_graph(method):
+    """An advance captured once in a graph (torch.cuda.CUDAGraph on the library's stream) and
+    replayed three times, with eager work in between, equals the eager advance each time."""
+    import torch
+
+    from gpu_helpers import DEV
+    from paper_2105_10332_amd.solver import HEAT, SweptSolver
+
+    N, M, tile = 96, 37, 32
+    T0 = problems.heat_sine_noise(N, seed=9)
+    x = torch.tensor(T0, device=DEV)
+    y = torch.empty_like(x)
+    dt = 0.2 / N / N
+    a = SweptSolver(HEAT, x, dt=dt, length=1.0, alpha=1.0, tile=tile)
+    b = SweptSolver(HEAT, y, dt=dt, length=1.0, alpha=1.0, tile=tile)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm the kernels before capture
+        getattr(a, method + "_advance")(1)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        getattr(a, method + "_advance")(M)
+    for _ in range(3):
+        y.copy_(x)
+        g.replay()
+        getattr(b, method + "_advance")(M)
+        torch.cuda.synchronize()
+        assert torch.equal(x, y)
+    a.close()
+    b.close()
