@@ -197,14 +197,16 @@ int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, voi
  * the tile must satisfy the LDS limit of the reverse shapes (tile <= 32). */
 
 /* Bytes of tape for an n_steps adjoint: ceil(n_steps/h) checkpoints, four
- * state-sized scratch buffers, two double planes for lambda (carried in
- * double for both state precisions), (n_steps mod h) stored levels and the
- * partial sums.  SWEPT_ENOTSUP for Euler, SWEPT_ESHAPE if the tile is too
+ * state-sized buffers per full cycle (the forward's Up-Pyramid and Bridge
+ * strips, kept so that the reverse sweep need not recompute them), two
+ * double planes for lambda (carried in double for both state precisions),
+ * (n_steps mod h) stored levels and the partial sums.  SWEPT_ENOTSUP for Euler, SWEPT_ESHAPE if the tile is too
  * large for the adjoint. */
 int swept_tape_bytes(const swept_ctx* ctx, int64_t n_steps, size_t* bytes);
 
-/* swept_advance(n_steps) that also records the checkpoints in d_tape (device
- * memory of swept_tape_bytes bytes, caller-owned).  Asynchronous. */
+/* swept_advance(n_steps) that also records the checkpoints and each cycle's
+ * forward strips in d_tape (device memory of swept_tape_bytes bytes,
+ * caller-owned).  Same result as swept_advance.  Asynchronous. */
 int swept_advance_checkpointed(swept_ctx* ctx, int64_t n_steps, void* d_tape, size_t tape_bytes);
 
 /* Reverse sweep for the run recorded in d_tape (same ctx and n_steps):

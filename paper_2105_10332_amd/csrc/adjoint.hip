@@ -9,10 +9,10 @@
 // where lambda^m is computed.
 //
 // The forward run is cut into cycles of h = b/2 steps with the flat state at
-// each cycle start kept as a checkpoint.  Backward, per cycle:
-//   F0 forward Up-Pyramid of the cycle from the checkpoint, strips -> P;
-//   F1 forward Bridges from P and the checkpoint, strips -> Q (so the
-//      Up-Pyramid's strips in P stay intact);
+// each cycle start kept as a checkpoint, and each cycle's forward strips kept
+// on the tape: the Up-Pyramid's in P, the Bridges' in Q (the first
+// Octahedron reads every ring cell from its owner's buffers).  Backward,
+// per cycle:
 //   R0, R1, R2 (this file): lambda over the cycle is itself a swept advance
 //      of h levels in reversed time k = h - j, starting flat, on the other
 //      tiling.  Its k-time Up-Pyramid, Bridges and Down-Pyramid occupy

@@ -148,7 +148,7 @@ struct TapePlan {
     int64_t nck;          // checkpoints: one per cycle start, plus the remainder's start
     int pk_max;           // packed forward levels per reverse workgroup
     int std_blocks;       // blocks of the remainder's one-step adjoint kernel
-    size_t ck_off, pairs_off, stash_off, part_off, total;
+    size_t ck_off, strips_off, pairs_off, stash_off, part_off, total;
     int64_t nparts;
 };
 
@@ -165,8 +165,11 @@ int tape_plan(const Derived& d, int nx, int64_t n_steps, TapePlan* t)
     t->std_blocks = kStdAdjBlocks;
     const size_t S = align_up(d.state_bytes), SL = align_up(sizeof(double) * (size_t)nx * nx);
     t->ck_off = 0;
-    t->pairs_off = t->ck_off + S * (size_t)t->nck;
-    t->stash_off = t->pairs_off + 4 * S + 2 * SL;  // P0 P1 Q0 Q1 (state type), L0 L1 (lambda, double)
+    // per cycle, the forward's Up-Pyramid strips (P0 P1) and Bridge strips (Q0 Q1), kept so that
+    // the reverse sweep need not recompute them
+    t->strips_off = t->ck_off + S * (size_t)t->nck;
+    t->pairs_off = t->strips_off + 4 * S * (size_t)t->cycles;
+    t->stash_off = t->pairs_off + 2 * SL;  // L0 L1 (lambda, double)
     t->part_off = t->stash_off + S * (size_t)t->rem;
     t->nparts = t->cycles * 4 * (int64_t)tiles * tiles + t->rem * kStdAdjBlocks;
     t->total = t->part_off + align_up(sizeof(double) * (size_t)(t->nparts + 1 + kAdjCombine));
@@ -428,12 +431,41 @@ int swept_advance_checkpointed(swept_ctx* c, int64_t n_steps, void* d_tape, size
     if (tape_bytes < t.total) return fail(SWEPT_EWORKSPACE, "tape %zu bytes < %zu needed", tape_bytes, t.total);
     char* tape = static_cast<char*>(d_tape);
     const size_t S = align_up(c->d.state_bytes);
+    const int h = c->d.h;
     for (int64_t k = 0; k < t.nck; ++k) {
         hipError_t e = hipMemcpyAsync(tape + t.ck_off + S * k, c->state, c->d.state_bytes, hipMemcpyDeviceToDevice,
                                       c->stream);
         if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
-        rc = advance_impl(c, k < t.cycles ? c->d.h : t.rem);
-        if (rc) return rc;
+        if (k == t.cycles) {  // the remainder: a plain advance
+            rc = advance_impl(c, t.rem);
+            if (rc) return rc;
+            continue;
+        }
+        // one flat-to-flat cycle of h steps: Up-Pyramid strips -> P, Bridge strips -> Q (both kept
+        // on the tape), then the first Octahedron, clipped at h, from P, Q and the flat state
+        char* pq = tape + t.strips_off + 4 * S * (size_t)k;
+        swept::PhaseArgs a = phase_args(c, h);
+        a.buf0 = a.out0 = pq;
+        a.buf1 = a.out1 = pq + S;
+        a.phase = 0;
+        e = swept::launch_phase(c->prob.kind, c->prob.dtype, a, c->d.wg, c->d.lds_bytes, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "taped Up-Pyramid");
+        a.out0 = pq + 2 * S;
+        a.out1 = pq + 3 * S;
+        a.phase = 1;
+        e = swept::launch_phase(c->prob.kind, c->prob.dtype, a, c->d.wg, c->d.lds_bytes, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "taped Bridges");
+        a.q0 = pq + 2 * S;
+        a.q1 = pq + 3 * S;
+        a.out0 = c->state;
+        a.out1 = c->buf1;
+        a.phase = 2;
+        e = swept::launch_phase(c->prob.kind, c->prob.dtype, a, c->d.wg, c->d.lds_bytes, c->stream);
+        if (e != hipSuccess) return hip_fail(e, "taped Octahedron");
+        if (h & 1) {  // level h lives in buffer 1
+            e = hipMemcpyAsync(c->state, c->buf1, c->d.state_bytes, hipMemcpyDeviceToDevice, c->stream);
+            if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+        }
     }
     return SWEPT_OK;
 }
@@ -449,13 +481,9 @@ int swept_adjoint(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes
     char* tape = static_cast<char*>(d_tape);
     const size_t S = align_up(c->d.state_bytes), SB = c->d.state_bytes;
     auto ck = [&](int64_t k) { return static_cast<void*>(tape + t.ck_off + S * k); };
-    void* P0 = tape + t.pairs_off;
-    void* P1 = tape + t.pairs_off + S;
-    void* Q0 = tape + t.pairs_off + 2 * S;
-    void* Q1 = tape + t.pairs_off + 3 * S;
     const size_t SL = align_up(sizeof(double) * (size_t)c->prob.nx * c->prob.nx);
-    void* La = tape + t.pairs_off + 4 * S;  // lambda (double) at the start of the next reverse step / cycle
-    void* Lb = tape + t.pairs_off + 4 * S + SL;
+    void* La = tape + t.pairs_off;  // lambda (double) at the start of the next reverse step / cycle
+    void* Lb = tape + t.pairs_off + SL;
     double* parts = reinterpret_cast<double*>(tape + t.part_off);
     const int N = c->prob.nx, tiles = N / c->d.tile, t2 = tiles * tiles, h = c->d.h;
     hipStream_t st = c->stream;
@@ -480,19 +508,12 @@ int swept_adjoint(swept_ctx* c, int64_t n_steps, void* d_tape, size_t tape_bytes
         if (e != hipSuccess) return hip_fail(e, "adjoint remainder");
     }
     for (int64_t cyc = t.cycles - 1; cyc >= 0; --cyc) {
-        // forward Up-Pyramid -> P, forward Bridges -> Q (level 0 from the checkpoint)
-        swept::PhaseArgs f = phase_args(c, h);
-        f.buf0 = f.out0 = P0;
-        f.buf1 = f.out1 = P1;
-        f.lvl0 = ck(cyc);
-        f.phase = 0;
-        e = swept::launch_phase(SWEPT_HEAT, c->prob.dtype, f, c->d.wg, c->d.lds_bytes, st);
-        if (e != hipSuccess) return hip_fail(e, "adjoint forward phase");
-        f.out0 = Q0;
-        f.out1 = Q1;
-        f.phase = 1;
-        e = swept::launch_phase(SWEPT_HEAT, c->prob.dtype, f, c->d.wg, c->d.lds_bytes, st);
-        if (e != hipSuccess) return hip_fail(e, "adjoint forward phase");
+        // the cycle's forward strips, kept by the checkpointed advance: Up-Pyramid (P), Bridges (Q)
+        char* pq = tape + t.strips_off + 4 * S * (size_t)cyc;
+        void* P0 = pq;
+        void* P1 = pq + S;
+        void* Q0 = pq + 2 * S;
+        void* Q1 = pq + 3 * S;
         // reverse phases on the other tiling
         swept::PhaseArgs a = phase_args(c, h);
         a.buf0 = P0;

@@ -460,7 +460,7 @@ constexpr int max_wg()
 // phase kernel, also run by the batched persistent kernel.  B > 0 fixes the
 // tile edge at compile time (a.tile must equal it), which turns the window
 // pitch into an immediate in every LDS address; B = 0 takes a.tile.
-template <class S, typename T, int B = 0>
+template <class S, typename T, int B = 0, bool TAPED = false>
 __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsigned char* smem_raw)
 {
     // heat, and Euler with walls: windows that cross the domain edge first (heat -2.7% FP64,
@@ -524,8 +524,11 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
     T* g1 = reinterpret_cast<T*>(a.out1);
     const int BUF = NVAR * P;  // LDS values per level-parity buffer (address arithmetic keeps ds_* access)
 
+    // TAPED (the adjoint's taped cycle, first Octahedron): the Up-Pyramid's strips are in
+    // buf0/buf1 and the Bridges' in q0/q1, and each ring cell comes from its owner's buffers
     const RingSrc<T> src{reinterpret_cast<const T*>(a.buf0), reinterpret_cast<const T*>(a.buf1),
-                         reinterpret_cast<const T*>(a.lvl0), nullptr, nullptr, false};
+                         reinterpret_cast<const T*>(a.lvl0), TAPED ? reinterpret_cast<const T*>(a.q0) : nullptr,
+                         TAPED ? reinterpret_cast<const T*>(a.q1) : nullptr, TAPED};
     preload_rings<S, T>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C);
     __syncthreads();
 

@@ -29,11 +29,11 @@
 namespace swept {
 
 // B > 0: heat instantiated for one tile edge (see phase_instance); B = 0: any tile.
-template <class S, typename T, int B>
+template <class S, typename T, int B, bool TAPED = false>
 __global__ void __launch_bounds__((max_wg<S, T>())) swept_phase_kernel(PhaseArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    phase_instance<S, T, B>(a, blockIdx.x, smem_raw);
+    phase_instance<S, T, B, TAPED>(a, blockIdx.x, smem_raw);
 }
 
 // ------------------------------------------------------------ Standard steps
@@ -216,15 +216,15 @@ __global__ void __launch_bounds__(256) cfl_partials(const T* __restrict__ q, siz
 
 // The phase kernel instantiation for a problem: heat at b = 16, 32 or 64
 // gets a fixed-tile copy, everything else the runtime-tile one.
-template <class S, typename T>
+template <class S, typename T, bool TAPED = false>
 static const void* phase_kernel(int tile)
 {
     if constexpr (S::NVAR == 1) {
-        if (tile == 64) return (const void*)swept_phase_kernel<S, T, 64>;
-        if (tile == 32) return (const void*)swept_phase_kernel<S, T, 32>;
-        if (tile == 16) return (const void*)swept_phase_kernel<S, T, 16>;
+        if (tile == 64) return (const void*)swept_phase_kernel<S, T, 64, TAPED>;
+        if (tile == 32) return (const void*)swept_phase_kernel<S, T, 32, TAPED>;
+        if (tile == 16) return (const void*)swept_phase_kernel<S, T, 16, TAPED>;
     }
-    return (const void*)swept_phase_kernel<S, T, 0>;
+    return (const void*)swept_phase_kernel<S, T, 0, TAPED>;
 }
 
 template <int V, int BC>
@@ -242,19 +242,21 @@ static const void* euler_phase_kernel(int dtype, int bc)
 }
 
 template <int BC>
-static const void* heat_phase_kernel(int dtype, int tile)
+static const void* heat_phase_kernel(int dtype, int tile, bool taped)
 {
+    if (taped)  // the first Octahedron of the adjoint's taped cycle (rings by owner)
+        return dtype == 0 ? phase_kernel<HeatSV<BC>, double, true>(tile) : phase_kernel<HeatSV<BC>, float, true>(tile);
     return dtype == 0 ? phase_kernel<HeatSV<BC>, double>(tile) : phase_kernel<HeatSV<BC>, float>(tile);
 }
 
 // scheme: Euler variant bits; bc: heat boundary.  Each combination is its own
 // instantiation, so the periodic minmod kernels carry no test for the others.
-static const void* phase_kernel(int kind, int dtype, int tile, int scheme, int bc)
+static const void* phase_kernel(int kind, int dtype, int tile, int scheme, int bc, bool taped = false)
 {
     if (kind == 0) {
-        if (bc == 1) return heat_phase_kernel<1>(dtype, tile);
-        if (bc == 2) return heat_phase_kernel<2>(dtype, tile);
-        return heat_phase_kernel<0>(dtype, tile);
+        if (bc == 1) return heat_phase_kernel<1>(dtype, tile, taped);
+        if (bc == 2) return heat_phase_kernel<2>(dtype, tile, taped);
+        return heat_phase_kernel<0>(dtype, tile, taped);
     }
     switch (scheme) {
         case 1: return euler_phase_kernel<1>(dtype, bc);
@@ -269,7 +271,8 @@ hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t 
     const int t2 = a.tiles * a.tiles;
     const int nblk = (a.phase & 1) ? 2 * t2 : t2;
     void* args[] = {(void*)&a};
-    return hipLaunchKernel(phase_kernel(kind, dtype, a.tile, a.scheme, a.bc), dim3(nblk), dim3(wg), args, lds, st);
+    return hipLaunchKernel(phase_kernel(kind, dtype, a.tile, a.scheme, a.bc, a.q0 != nullptr), dim3(nblk), dim3(wg),
+                           args, lds, st);
 }
 
 hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds)
@@ -278,9 +281,10 @@ hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds)
     for (int bc = 0; bc < 4; ++bc)  // heat: boundaries 0-2; Euler: boundaries 0, 2, 3 x scheme bits
         for (int v = 0; v < (kind == 0 ? 1 : 4); ++v)
             for (int tile : {0, 16, 32, 64})
-                if (e == hipSuccess && !(kind == 0 && bc == 3) && !(kind == 1 && bc == 1))
-                    e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile, v, bc),
-                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+                for (int taped = 0; taped < (kind == 0 ? 2 : 1); ++taped)
+                    if (e == hipSuccess && !(kind == 0 && bc == 3) && !(kind == 1 && bc == 1))
+                        e = hipFuncSetAttribute(phase_kernel(kind, dtype, tile, v, bc, taped != 0),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return e;
 }
 

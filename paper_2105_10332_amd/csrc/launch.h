@@ -37,7 +37,7 @@ struct PhaseArgs {
     void* out0;   // where stores go (normally buf0/buf1; the adjoint's Bridges recompute writes elsewhere)
     void* out1;
     const void* lvl0;  // level-0 state (normally buf0)
-    const void* q0;    // adjoint only: the Bridges' strips, read by the Octahedron recompute
+    const void* q0;    // adjoint only: the Bridges' strips, read by the first Octahedron of a taped cycle
     const void* q1;
     void* lam0;        // adjoint only: lambda level-parity buffers (reversed time)
     void* lam1;
