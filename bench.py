@@ -40,8 +40,8 @@ METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB
 # WRITE_SIZE x 1.0: the factors a plain copy of known size reads), keyed by workload and launch
 # shape, valid only for the kernel sources whose hash is recorded with it (null otherwise).
 MEASURED_TRAFFIC = {
-    ("heat", "f64", 4096, 64, 512, 1000): (629.1e6, "c169b8c64213ac64"),
-    ("heat", "f32", 4096, 64, 256, 1000): (447.4e6, "c169b8c64213ac64"),
+    ("heat", "f64", 4096, 64, 512, 1000): (633.8e6, "ea3f2236bc1cd7e7"),
+    ("heat", "f32", 4096, 64, 256, 1000): (417.4e6, "ea3f2236bc1cd7e7"),
 }
 KERNEL_SOURCES = ("scheme.h", "device_common.h", "kernels.hip", "launch.h")
 
