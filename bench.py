@@ -42,6 +42,14 @@ METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB
 MEASURED_TRAFFIC = {
     ("heat", "f64", 4096, 64, 512, 1000): (633.8e6, "ea3f2236bc1cd7e7"),
     ("heat", "f32", 4096, 64, 256, 1000): (417.4e6, "ea3f2236bc1cd7e7"),
+    ("euler", "f64", 2048, 16, 256, 500): (826.2e6, "ea3f2236bc1cd7e7"),
+    ("euler", "f32", 2048, 32, 512, 500): (469.3e6, "ea3f2236bc1cd7e7"),
+}
+# The same two passes over the Standard kernels: HBM bytes per launch (one time step).
+MEASURED_STANDARD_TRAFFIC = {
+    ("heat", "f64", 4096): (366.2e6, "ea3f2236bc1cd7e7"),
+    ("euler", "f64", 2048): (538.6e6, "ea3f2236bc1cd7e7"),
+    ("euler", "f32", 2048): (336.7e6, "ea3f2236bc1cd7e7"),
 }
 KERNEL_SOURCES = ("scheme.h", "device_common.h", "kernels.hip", "launch.h")
 
@@ -67,8 +75,8 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(key):
-    rec = MEASURED_TRAFFIC.get(key)
+def measured_traffic(key, table=MEASURED_TRAFFIC):
+    rec = table.get(key)
     return rec[0] if rec and rec[1] == kernel_hash() else None
 
 
@@ -214,6 +222,8 @@ def run_heat(args):
         ssec, _ = timed(lambda: ss.standard_advance(M), k)
         out["standard"] = {"value": n * n * M * k / ssec, "unit": "cell-updates/s", "ms_per_advance": ssec / k * 1e3,
                            "achieved_GBps": 2 * S * n * n * M * k / ssec / 1e9}
+        if args.boundary == 0:
+            out["standard"]["traffic_per_launch"] = measured_traffic(("heat", dt_name, n), MEASURED_STANDARD_TRAFFIC)
         out["speedup_vs_standard"] = rate / out["standard"]["value"]
     out["wall_s"] = wall
     if not args.no_cpu:
@@ -290,6 +300,8 @@ def run_euler(args):
     out = base_record(args, rate, "cell-steps/s", sec, dt_name, cfg)
     out["effective_GBps"] = 8 * S * cells / sec / 1e9
     out["roofline"] = roofline(plan, S, 4, plan["launches"] * args.steps, sec, "swept_phase_kernel<EulerS>")
+    if args.boundary == 0 and args.scheme == 0:
+        out["roofline"]["traffic"] = measured_traffic(("euler", dt_name, n, tile, solver.info.wg, M))
     if not args.no_standard:
         st = torch.tensor(Q0, dtype=tdt, device="cuda")
         ss = SweptSolver(EULER, st, dt=dt, length=10.0, gamma=1.4, tile=tile, scheme=args.scheme,
@@ -297,6 +309,8 @@ def run_euler(args):
         ss.standard_advance(M)
         ssec, _ = timed(lambda: ss.standard_advance(M), 1)
         out["standard"] = {"value": n * n * M / ssec, "unit": "cell-steps/s", "ms_per_advance": ssec * 1e3}
+        if args.boundary == 0 and args.scheme == 0:
+            out["standard"]["traffic_per_launch"] = measured_traffic(("euler", dt_name, n), MEASURED_STANDARD_TRAFFIC)
         out["speedup_vs_standard"] = rate / out["standard"]["value"]
     out["reductions"] = reductions(solver, q, S, n)
     out["wall_s"] = wall
