@@ -181,6 +181,25 @@ def roofline(plan, S, nvar, launches, sec, kernel):
             "traffic": None, "kernel": kernel, "alg_bytes_per_launch": alg, "avg_launch_us": avg * 1e6}
 
 
+# Per-update costs of the swept heat kernel beside its HBM bytes, for the bound
+# t_min = max(HBM bytes / HBM peak, flops / vector peak, LDS bytes / LDS peak): the 9 flops of
+# the 5-point update, and the LDS values of the pair-strip walk (per pair of cells the next row
+# of both columns and the outer left and right neighbours are read and both results written:
+# 3 values per update).  LDS peak: 128 B per clock per CU x 256 CUs x 2.4 GHz.
+LDS_PEAK_GBS = 128 * 256 * 2.4
+VECTOR_PEAK_TFLOPS = {8: 78.6, 4: 157.3}
+HEAT_FLOPS, HEAT_LDS_VALUES = 9, 3
+
+
+def heat_bounds(plan, S, updates_per_advance, rate):
+    t = {"hbm": (plan["loads"] + plan["stores"]) * S / updates_per_advance / (HBM_PEAK_GBS * 1e9),
+         "lds": HEAT_LDS_VALUES * S / (LDS_PEAK_GBS * 1e9),
+         "valu": HEAT_FLOPS / (VECTOR_PEAK_TFLOPS[S] * 1e12)}
+    return {"model": "t_min = max(HBM bytes/HBM peak, flops/vector peak, LDS bytes/LDS peak) per cell-update",
+            "ps_per_update": {k: v * 1e12 for k, v in t.items()},
+            "frac": {k: v * rate for k, v in t.items()}, "binding": max(t, key=t.get)}
+
+
 def run_heat(args):
     import numpy as np
     import torch
@@ -212,6 +231,7 @@ def run_heat(args):
     out = base_record(args, rate, "cell-updates/s", sec, dt_name, cfg)
     out["effective_GBps"] = 2 * S * updates / sec / 1e9
     out["roofline"] = roofline(plan, S, 1, plan["launches"] * args.steps, sec, "swept_phase_kernel<HeatS>")
+    out["bounds"] = heat_bounds(plan, S, n * n * M, rate)
     if args.boundary == 0:
         out["roofline"]["traffic"] = measured_traffic(("heat", dt_name, n, tile, solver.info.wg, M))
     if not args.no_standard:

@@ -89,3 +89,18 @@ def test_cpu_baseline_record():
     assert rec["kind"] == "oracle" and rec["unit"] == "cell-updates/s"
     assert rec["value"] > 0 and rec["cores"] >= 1
     assert "64x64" in rec["sample"]
+
+
+@pytest.mark.parametrize("S", [8, 4])
+def test_three_bound_model_agrees_with_the_roofline(S):
+    n, b, M = 4096, 64, 1000
+    plan = geometry.totals(n, b, 1, M)
+    sec = 0.032
+    rate = n * n * M / sec
+    rf = bench.roofline(plan, S, 1, plan["launches"], sec, "k")
+    bd = bench.heat_bounds(plan, S, n * n * M, rate)
+    assert bd["frac"]["hbm"] == pytest.approx(rf["frac"])
+    assert bd["binding"] == max(bd["frac"], key=bd["frac"].get)
+    # LDS: 3 values per update at 128 B/clk/CU over 256 CUs at 2.4 GHz
+    assert bd["ps_per_update"]["lds"] == pytest.approx(3 * S / (128 * 256 * 2.4e9) * 1e12)
+    assert bd["ps_per_update"]["valu"] == pytest.approx(9 / ({8: 78.6, 4: 157.3}[S] * 1e12) * 1e12)

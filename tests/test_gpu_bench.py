@@ -45,6 +45,7 @@ def test_bench_heat(dtype):
     assert rec["dtype"] == dtype and rec["unit"] == "cell-updates/s"
     check_roofline(rec)
     assert rec["standard"]["traffic_per_launch"] is None
+    assert rec["bounds"]["frac"]["hbm"] == pytest.approx(rec["roofline"]["frac"])
     assert rec["speedup_vs_standard"] == pytest.approx(rec["value"] / rec["standard"]["value"])
 
 
