@@ -230,7 +230,11 @@ int swept_destroy(swept_ctx* ctx);
  * second level-parity buffer and level table, the launch arguments and the
  * two phase counters; calls that overlap on one workspace race.  Workgroups have 512 threads (FP32) or 256 (FP64);
  * tunes[q].tile (or 0 = default) picks each problem's tile, tunes may be
- * NULL. */
+ * NULL.  swept_batch_advance is a cooperative launch: it has been seen to
+ * return SWEPT_EHIP (HIP: operation cannot be performed in the present state)
+ * in a process started while another live process on the same GPU had made
+ * cooperative launches; run batches from one process per GPU.  The
+ * single-problem calls have no such limit. */
 typedef struct swept_batch swept_batch;
 
 int swept_batch_workspace_bytes(const swept_problem* probs, const swept_tuning* tunes, int32_t count,
