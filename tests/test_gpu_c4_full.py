@@ -1,0 +1,77 @@
+"""The Euler vortex workload at its full size and length (2048^2 on [0,10]^2, CFL 0.4,
+500 RK2 steps) in the launch configurations the benchmark times: FP64 tile 16 with 256
+threads, FP32 tile 32 with 512.  Swept equals Standard bit for bit, FP64 equals the
+oracle's 500 steps within 1e-10 (0 measured), FP32 equals the FP32 oracle's within 1e-5,
+mass, momentum and energy are conserved to roundoff, and the FP32 error against the FP64
+oracle is stated (3.5e-3 measured)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2105_10332_amd import problems
+from paper_2105_10332_amd.solver import EULER, SweptSolver, swept_cfl_dt
+
+from gpu_helpers import DEV, rel_err
+
+pytestmark = pytest.mark.gpu
+GAMMA, N, STEPS, LENGTH = 1.4, 2048, 500, 10.0
+
+
+@pytest.fixture(scope="module")
+def c4():
+    Q0 = problems.shu_vortex(N)
+    dt = swept_cfl_dt(torch.tensor(Q0, device=DEV), LENGTH, 0.4)
+    print(f"C4 oracle: {N}^2, {STEPS} steps, dt {dt:.7e}", flush=True)
+    ref = oracle.euler_run(Q0, dt, LENGTH / N, LENGTH / N, GAMMA, STEPS)
+    return Q0, dt, ref
+
+
+@pytest.fixture(scope="module")
+def c4_fp32_ref(c4):
+    Q0, dt, _ = c4
+    return oracle.euler_run(Q0.astype(np.float32), dt, LENGTH / N, LENGTH / N, GAMMA, STEPS)
+
+
+def run(Q0, dt, dtype, tile, wg, method):
+    Q = torch.tensor(Q0, dtype=dtype, device=DEV)
+    s = SweptSolver(EULER, Q, dt=dt, length=LENGTH, gamma=GAMMA, tile=tile, wg=wg)
+    before = np.array(s.swept_conserved())
+    getattr(s, method + "_advance")(STEPS)
+    after = np.array(s.swept_conserved())
+    torch.cuda.synchronize()
+    s.close()
+    return Q.cpu().numpy(), before, after
+
+
+def test_c4_fp64_full_length(c4):
+    Q0, dt, ref = c4
+    assert abs(dt - 3.621859e-4) < 1e-9
+    sw, b0, b1 = run(Q0, dt, torch.float64, 16, 256, "swept")
+    st, _, _ = run(Q0, dt, torch.float64, 16, 256, "standard")
+    assert np.isfinite(sw).all()
+    assert np.array_equal(sw, st)
+    err = rel_err(sw, ref)
+    print(f"C4 FP64 swept vs oracle after {STEPS} steps: {err:.3e}")
+    assert err <= 1e-10
+    scale = np.abs(Q0).reshape(4, -1).sum(axis=1)
+    assert np.all(np.abs(b1 - b0) / scale < 1e-12)
+
+
+def test_c4_fp32_full_length(c4, c4_fp32_ref):
+    Q0, dt, ref = c4
+    sw, b0, b1 = run(Q0, dt, torch.float32, 32, 512, "swept")
+    st, _, _ = run(Q0, dt, torch.float32, 32, 512, "standard")
+    assert np.isfinite(sw).all()
+    assert np.array_equal(sw, st)
+    err32 = rel_err(sw, c4_fp32_ref)
+    err = rel_err(sw, ref)
+    print(f"C4 FP32 swept after {STEPS} steps: vs FP32 oracle {err32:.3e}, vs FP64 oracle {err:.3e}")
+    assert err32 <= 1e-5
+    assert err <= 1e-2
+    scale = np.abs(Q0).reshape(4, -1).sum(axis=1)
+    drift = np.abs(b1 - b0) / scale
+    print(f"C4 FP32 conserved-sum drift (FP64 sums of the FP32 state): {drift.max():.3e}")
+    assert np.all(drift < 1e-5)
