@@ -10,8 +10,10 @@ in place.
 Reported: cell-updates/s of the swept solver (value), the Standard
 solver's rate on the same input and the paper's speedup S = R_standard /
 R_swept (Eq. 3), the effective bandwidth (bytes the Standard solver would
-move / time), the roofline of the dominant kernel (the swept phase kernel)
-and the CPU oracle timed on a bounded sample of the same workload.
+move / time), the roofline of the dominant kernel (the swept phase kernel),
+its three per-update bounds (HBM bytes, vector-ALU flops, LDS bytes; heat only),
+the HBM traffic the counters measured for this build (else null) and the CPU
+oracle timed on a bounded sample of the same workload.
 
 Other workloads (--workload): euler (2048^2 vortex, 500 RK2 steps per
 step), adjoint (1024^2 FP32 heat, 2000 steps: forward with checkpoints +
