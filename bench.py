@@ -12,7 +12,7 @@ solver's rate on the same input and the paper's speedup S = R_standard /
 R_swept (Eq. 3), the effective bandwidth (bytes the Standard solver would
 move / time), the roofline of the dominant kernel (the swept phase kernel),
 its three per-update bounds (HBM bytes, vector-ALU flops, LDS bytes; heat only),
-the HBM traffic the counters measured for this build (else null) and the CPU
+the HBM traffic the counters measured for these kernel sources (else null) and the CPU
 oracle timed on a bounded sample of the same workload.
 
 Other workloads (--workload): euler (2048^2 vortex, 500 RK2 steps per
