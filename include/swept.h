@@ -230,20 +230,28 @@ int swept_destroy(swept_ctx* ctx);
  * second level-parity buffer and level table, the launch arguments and the
  * two phase counters; calls that overlap on one workspace race.  Workgroups have 512 threads (FP32) or 256 (FP64);
  * tunes[q].tile (or 0 = default) picks each problem's tile, tunes may be
- * NULL.  swept_batch_advance is a cooperative launch: it has been seen to
- * return SWEPT_EHIP (HIP: operation cannot be performed in the present state)
- * in a process started while another live process on the same GPU had made
- * cooperative launches; run batches from one process per GPU.  The
- * single-problem calls have no such limit. */
+ * NULL.  swept_batch_advance is by default a cooperative launch: it has been
+ * seen to return SWEPT_EHIP (HIP: operation cannot be performed in the
+ * present state) in a process started while another live process on the same
+ * GPU had made cooperative launches.  Such a process can switch the batch to
+ * one ordinary launch per global phase (swept_batch_set_mode), where stream
+ * order replaces the grid barrier; the results are the same bit for bit. */
 typedef struct swept_batch swept_batch;
+
+#define SWEPT_BATCH_COOPERATIVE 0 /* one persistent launch per advance (default) */
+#define SWEPT_BATCH_PER_PHASE 1   /* one launch per global phase */
 
 int swept_batch_workspace_bytes(const swept_problem* probs, const swept_tuning* tunes, int32_t count,
                                 size_t* bytes);
 /* d_states[q]: problem q's state (layout as above), advanced in place. */
 int swept_batch_init(swept_batch** ctx, const swept_problem* probs, const swept_tuning* tunes,
                      void* const* d_states, int32_t count, void* d_work, size_t work_bytes, void* hip_stream);
-/* n_steps time steps for every problem, one persistent launch.  Asynchronous. */
+/* n_steps time steps for every problem: one persistent launch, or one launch
+ * per global phase in SWEPT_BATCH_PER_PHASE mode.  Asynchronous. */
 int swept_batch_advance(swept_batch* ctx, int64_t n_steps);
+/* SWEPT_BATCH_COOPERATIVE or SWEPT_BATCH_PER_PHASE for later advances;
+ * SWEPT_EINVAL for any other value. */
+int swept_batch_set_mode(swept_batch* ctx, int32_t mode);
 int swept_batch_query(const swept_batch* ctx, int32_t q, swept_info* info);
 /* Workgroups of the persistent launch (resident capacity for its LDS). */
 int swept_batch_grid(const swept_batch* ctx, int32_t* grid);

@@ -22,6 +22,7 @@ HEAT, EULER = 0, 1
 F64, F32 = 0, 1
 LIMITER_LITERAL, SPEED_ROE = 1, 2  # Euler scheme variant bits (swept.h)
 BC_PERIODIC, BC_DIRICHLET, BC_NEUMANN, BC_REFLECT = 0, 1, 2, 3  # boundaries (swept.h)
+BATCH_COOPERATIVE, BATCH_PER_PHASE = 0, 1  # batch launch modes (swept.h)
 
 
 class SweptError(RuntimeError):
@@ -71,6 +72,7 @@ _SIGS = {
     "swept_batch_advance": [_P, ctypes.c_int64],
     "swept_batch_query": [_P, ctypes.c_int32, ctypes.POINTER(Info)],
     "swept_batch_grid": [_P, ctypes.POINTER(ctypes.c_int32)],
+    "swept_batch_set_mode": [_P, ctypes.c_int32],
     "swept_batch_set_stream": [_P, _P],
     "swept_batch_destroy": [_P],
 }

@@ -46,6 +46,49 @@ __device__ __forceinline__ void instance(const PhaseArgs& a, int blk, unsigned c
     }
 }
 
+// Global phase gp of the batch, run by every workgroup of the grid: the items
+// of the phase problem by problem (prefix in pre), then the instances.
+template <typename T>
+__device__ __forceinline__ void batch_phase(const PhaseArgs* __restrict__ probs, int count, int gp, long long n_steps,
+                                            int* ctr, int* pre, int* s_it, unsigned char* smem_raw)
+{
+    if (threadIdx.x == 0) {  // items of this global phase, problem by problem
+        int tot = 0;
+        for (int q = 0; q < count; ++q) {
+            pre[q] = tot;
+            const PhaseArgs& a = probs[q];
+            const int t2 = a.tiles * a.tiles;
+            if (gp < problem_phases(a, n_steps)) tot += (gp & 1) ? 2 * t2 : t2;
+        }
+        pre[count] = tot;
+        if (blockIdx.x == 0) ctr[(gp + 1) & 1] = 0;  // the next phase's counter is idle during this one
+    }
+    __syncthreads();
+    const int total = pre[count];
+    for (int k = 0;; ++k) {
+        int it;
+        if (gp == 0) {
+            it = blockIdx.x + k * gridDim.x;
+        } else {
+            if (threadIdx.x == 0) *s_it = atomicAdd(&ctr[gp & 1], 1);
+            __syncthreads();
+            it = *s_it;
+        }
+        if (it >= total) break;
+        int lo = 0, hi = count;  // largest q with pre[q] <= it
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        PhaseArgs a = probs[lo];
+        a.phase = gp;
+        a.L = (int)(n_steps * (a.kind == 0 ? 1 : 2));
+        instance<T>(a, it - pre[lo], smem_raw);
+        __syncthreads();
+    }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
     batch_kernel(const PhaseArgs* __restrict__ probs, int count, int nphase_max, long long n_steps, int* ctr)
@@ -55,43 +98,21 @@ __global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
     __shared__ int s_it;
     cg::grid_group grid = cg::this_grid();
     for (int gp = 0; gp < nphase_max; ++gp) {
-        if (threadIdx.x == 0) {  // items of this global phase, problem by problem
-            int tot = 0;
-            for (int q = 0; q < count; ++q) {
-                pre[q] = tot;
-                const PhaseArgs& a = probs[q];
-                const int t2 = a.tiles * a.tiles;
-                if (gp < problem_phases(a, n_steps)) tot += (gp & 1) ? 2 * t2 : t2;
-            }
-            pre[count] = tot;
-            if (blockIdx.x == 0) ctr[(gp + 1) & 1] = 0;  // the next phase's counter is idle during this one
-        }
-        __syncthreads();
-        const int total = pre[count];
-        for (int k = 0;; ++k) {
-            int it;
-            if (gp == 0) {
-                it = blockIdx.x + k * gridDim.x;
-            } else {
-                if (threadIdx.x == 0) s_it = atomicAdd(&ctr[gp & 1], 1);
-                __syncthreads();
-                it = s_it;
-            }
-            if (it >= total) break;
-            int lo = 0, hi = count;  // largest q with pre[q] <= it
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (pre[mid] <= it) lo = mid;
-                else hi = mid;
-            }
-            PhaseArgs a = probs[lo];
-            a.phase = gp;
-            a.L = (int)(n_steps * (a.kind == 0 ? 1 : 2));
-            instance<T>(a, it - pre[lo], smem_raw);
-            __syncthreads();
-        }
+        batch_phase<T>(probs, count, gp, n_steps, ctr, pre, &s_it, smem_raw);
         grid.sync();
     }
+}
+
+// One global phase per launch: the same work with stream order in place of the
+// grid barrier, for processes that cannot make cooperative launches.
+template <typename T>
+__global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
+    batch_phase_kernel(const PhaseArgs* __restrict__ probs, int count, int gp, long long n_steps, int* ctr)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ int pre[kBatchMax + 1];
+    __shared__ int s_it;
+    batch_phase<T>(probs, count, gp, n_steps, ctr, pre, &s_it, smem_raw);
 }
 
 hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu)
@@ -103,7 +124,10 @@ hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu)
 hipError_t set_batch_lds_limit(int dtype, size_t lds)
 {
     const void* f = dtype == 0 ? (const void*)batch_kernel<double> : (const void*)batch_kernel<float>;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void* g = dtype == 0 ? (const void*)batch_phase_kernel<double> : (const void*)batch_phase_kernel<float>;
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) e = hipFuncSetAttribute(g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return e;
 }
 
 hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphase_max, long long n_steps, int grid,
@@ -112,6 +136,18 @@ hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphas
     void* args[] = {(void*)&d_args, (void*)&count, (void*)&nphase_max, (void*)&n_steps, (void*)&ctr};
     const void* f = dtype == 0 ? (const void*)batch_kernel<double> : (const void*)batch_kernel<float>;
     return hipLaunchCooperativeKernel(f, dim3(grid), dim3(batch_wg(dtype)), args, (unsigned int)lds, st);
+}
+
+hipError_t launch_batch_phase(int dtype, const PhaseArgs* d_args, int count, int gp, long long n_steps, int grid,
+                              size_t lds, hipStream_t st, int* ctr)
+{
+    if (dtype == 0)
+        hipLaunchKernelGGL(batch_phase_kernel<double>, dim3(grid), dim3(batch_wg(dtype)), lds, st, d_args, count, gp,
+                           n_steps, ctr);
+    else
+        hipLaunchKernelGGL(batch_phase_kernel<float>, dim3(grid), dim3(batch_wg(dtype)), lds, st, d_args, count, gp,
+                           n_steps, ctr);
+    return hipGetLastError();
 }
 
 }  // namespace swept

@@ -643,6 +643,7 @@ struct swept_batch {
     int* ctr = nullptr;
     size_t lds = 0;
     int grid = 0;
+    int mode = SWEPT_BATCH_COOPERATIVE;
 };
 
 namespace {
@@ -793,8 +794,15 @@ int swept_batch_advance(swept_batch* b, int64_t n_steps)
         const int64_t L = n_steps * b->d[q].lps;
         nph = std::max(nph, (int)(2 * ((L + b->d[q].h - 1) / b->d[q].h) + 1));
     }
-    hipError_t e = swept::launch_batch(b->dtype, b->dev_args, b->count, nph, (long long)n_steps, b->grid, b->lds,
-                                       b->stream, b->ctr);
+    hipError_t e = hipSuccess;
+    if (b->mode == SWEPT_BATCH_COOPERATIVE) {
+        e = swept::launch_batch(b->dtype, b->dev_args, b->count, nph, (long long)n_steps, b->grid, b->lds, b->stream,
+                                b->ctr);
+    } else {
+        for (int gp = 0; gp < nph && e == hipSuccess; ++gp)
+            e = swept::launch_batch_phase(b->dtype, b->dev_args, b->count, gp, (long long)n_steps, b->grid, b->lds,
+                                          b->stream, b->ctr);
+    }
     if (e != hipSuccess) return hip_fail(e, "batch launch");
     for (int q = 0; q < b->count; ++q) {
         if ((n_steps * b->d[q].lps) & 1) {
@@ -802,6 +810,15 @@ int swept_batch_advance(swept_batch* b, int64_t n_steps)
             if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
         }
     }
+    return SWEPT_OK;
+}
+
+int swept_batch_set_mode(swept_batch* b, int32_t mode)
+{
+    if (!b) return fail(SWEPT_EINVAL, "ctx is NULL");
+    if (mode != SWEPT_BATCH_COOPERATIVE && mode != SWEPT_BATCH_PER_PHASE)
+        return fail(SWEPT_EINVAL, "batch mode %d is neither cooperative (0) nor per phase (1)", (int)mode);
+    b->mode = mode;
     return SWEPT_OK;
 }
 

@@ -91,6 +91,9 @@ hipError_t batch_occupancy(int dtype, size_t lds, int* blocks_per_cu);
 hipError_t set_batch_lds_limit(int dtype, size_t lds);
 hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphase_max, long long n_steps, int grid,
                         size_t lds, hipStream_t st, int* ctr);
+// Global phase gp alone, as an ordinary launch (the batch's one-launch-per-phase mode).
+hipError_t launch_batch_phase(int dtype, const PhaseArgs* d_args, int count, int gp, long long n_steps, int grid,
+                              size_t lds, hipStream_t st, int* ctr);
 hipError_t launch_combine(const double* partials, int nparts, double* out, hipStream_t st);
 hipError_t launch_plane_sums(int dtype, const void* x, int nvar, size_t NN, double* partials, int nparts,
                              double* out, hipStream_t st);

@@ -12,8 +12,8 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import (BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC, BC_REFLECT, EULER, F32, F64, HEAT, LIMITER_LITERAL,
-                   SPEED_ROE, Info, Problem, Tuning, check, lib)
+from ._lib import (BATCH_COOPERATIVE, BATCH_PER_PHASE, BC_DIRICHLET, BC_NEUMANN, BC_PERIODIC, BC_REFLECT, EULER, F32,
+                   F64, HEAT, LIMITER_LITERAL, SPEED_ROE, Info, Problem, Tuning, check, lib)
 
 _DT = {torch.float64: F64, torch.float32: F32}
 
@@ -158,6 +158,11 @@ class SweptBatch:
         check(lib().swept_batch_set_stream(self._ctx, _stream_ptr()))
         check(lib().swept_batch_advance(self._ctx, int(n_steps)))
 
+    def swept_batch_set_mode(self, mode: int):
+        """BATCH_COOPERATIVE (one persistent launch, the default) or BATCH_PER_PHASE (one
+        launch per global phase, for processes that cannot make cooperative launches)."""
+        check(lib().swept_batch_set_mode(self._ctx, int(mode)))
+
     def info(self, q: int) -> Info:
         inf = Info()
         check(lib().swept_batch_query(self._ctx, q, ctypes.byref(inf)))
@@ -230,4 +235,4 @@ def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 
 
 __all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT",
            "EULER", "LIMITER_LITERAL", "SPEED_ROE", "BC_PERIODIC", "BC_DIRICHLET", "BC_NEUMANN",
-           "BC_REFLECT", "_lib"]
+           "BC_REFLECT", "BATCH_COOPERATIVE", "BATCH_PER_PHASE", "_lib"]

@@ -148,3 +148,11 @@ def test_batch_count_and_dtype_validation():
     assert L.swept_batch_workspace_bytes(walls, None, 1, ctypes.byref(out)) == 0  # walls batch too
     for bc in (1, 2):  # the single-problem heat path takes both
         assert _ws(Problem(0, 0, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4, 0, bc, 0.25), 16)[0] == 0
+
+
+def test_batch_mode_validation():
+    """swept_batch_set_mode checks its context before anything else."""
+    L = _lib.lib()
+    for mode in (0, 1, 2, -1):
+        assert L.swept_batch_set_mode(None, mode) == CODES["SWEPT_EINVAL"]
+    assert _lib.BATCH_COOPERATIVE == 0 and _lib.BATCH_PER_PHASE == 1

@@ -5,7 +5,7 @@ import torch
 
 import oracle
 from paper_2105_10332_amd import problems
-from paper_2105_10332_amd.solver import EULER, HEAT, SweptBatch, SweptSolver
+from paper_2105_10332_amd.solver import BATCH_PER_PHASE, EULER, HEAT, SweptBatch, SweptSolver
 
 from gpu_helpers import DEV, rel_err
 
@@ -113,3 +113,45 @@ def test_batch_largest_count():
     torch.cuda.synchronize()
     for q, ((kind, x, *_), y) in enumerate(zip(items, refs)):
         assert torch.equal(x, y), (q, spec[q])
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+@pytest.mark.parametrize("steps", [1, 13, 40])
+def test_per_phase_mode_equals_standalone(dtype, steps):
+    """One ordinary launch per global phase gives every problem's own swept advance bit for bit."""
+    items = _items(dtype, SPEC)
+    refs = []
+    for kind, x, dt, length, alpha, gamma, tile in items:
+        y = x.clone()
+        s = SweptSolver(kind, y, dt=dt, length=length, alpha=alpha, gamma=gamma, tile=tile)
+        s.swept_advance(steps)
+        refs.append(y)
+        s.close()
+    b = SweptBatch(items)
+    b.swept_batch_set_mode(BATCH_PER_PHASE)
+    b.swept_batch_advance(steps)
+    torch.cuda.synchronize()
+    for q, ((kind, x, *_), y) in enumerate(zip(items, refs)):
+        assert torch.equal(x, y), (q, SPEC[q])
+
+
+def test_modes_alternate_on_one_batch():
+    """Advances in the two modes on one batch (the phase counters carried between them) against
+    the oracle, FP64."""
+    items = _items(torch.float64, SPEC[:5])
+    init = [it[1].cpu().numpy().copy() for it in items]
+    b = SweptBatch(items)
+    b.swept_batch_set_mode(BATCH_PER_PHASE)
+    b.swept_batch_advance(7)
+    b.swept_batch_set_mode(0)
+    b.swept_batch_advance(11)
+    b.swept_batch_set_mode(BATCH_PER_PHASE)
+    b.swept_batch_advance(5)
+    torch.cuda.synchronize()
+    for q, (kind, x, dt, length, alpha, gamma, tile) in enumerate(items):
+        n = x.shape[-1]
+        if kind == HEAT:
+            ref = oracle.heat_run(init[q], b.info(q).r, 23)
+        else:
+            ref = oracle.euler_run(init[q], dt, 10 / n, 10 / n, 1.4, 23)
+        assert rel_err(x.cpu().numpy(), ref) <= 1e-10
