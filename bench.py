@@ -102,6 +102,8 @@ def parse():
     ap.add_argument("--advance-steps", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-standard", action="store_true")
+    ap.add_argument("--batch-per-phase", action="store_true",
+                    help="batch workload: one ordinary launch per global phase instead of one cooperative launch")
     ap.add_argument("--copy-reference", action="store_true",
                     help="only run a plain device copy of the C2 state size (calibrates rocprofv3 FETCH/WRITE_SIZE)")
     return ap.parse_args()
@@ -390,7 +392,7 @@ def run_batch(args):
     import torch
 
     from paper_2105_10332_amd import problems, tune
-    from paper_2105_10332_amd.solver import EULER, HEAT, SweptBatch, SweptSolver, swept_cfl_dt
+    from paper_2105_10332_amd.solver import BATCH_PER_PHASE, EULER, HEAT, SweptBatch, SweptSolver, swept_cfl_dt
 
     dt_name = args.dtype or "f32"
     tdt = torch.float64 if dt_name == "f64" else torch.float32
@@ -410,6 +412,8 @@ def run_batch(args):
         cells += n * n * M
     init = [it[1].clone() for it in items]
     b = SweptBatch(items)
+    if args.batch_per_phase:
+        b.swept_batch_set_mode(BATCH_PER_PHASE)
 
     def one():
         for it, x0 in zip(items, init):
@@ -429,7 +433,9 @@ def run_batch(args):
 
     ssec, _ = timed(seq, 1)
     cfg = {"workload": f"batch of 48 heat (edges 128-1024, r 0.05-0.24) + 16 Euler vortex (edges 256-1024, "
-                       f"eps 1-5) problems, {M} steps each, one persistent launch; grid {b.grid} workgroups",
+                       f"eps 1-5) problems, {M} steps each, "
+                       f"{'one launch per global phase' if args.batch_per_phase else 'one persistent launch'}; "
+                       f"grid {b.grid} workgroups",
            "problems": len(items), "grid": b.grid,
            "tiles": {"heat": sorted(set(t for it, t in zip(ens, tiles) if it.kind == "heat")),
                      "euler": sorted(set(t for it, t in zip(ens, tiles) if it.kind == "euler"))}}

@@ -60,9 +60,13 @@ def test_bench_adjoint():
     rec = run_bench("--workload", "adjoint", "--n", "256", "--advance-steps", "64")
     assert rec["value"] > 0 and rec["adjoint_over_forward"] > 0
 
-# The batch workload is not run from here: its cooperative launch has failed to start in a
-# second process while this one (the test runner, after the batch tests) was alive with
-# cooperative launches of its own; the batch tests cover that path in this process.
+
+def test_bench_batch_per_phase():
+    # one launch per global phase: a cooperative launch has failed to start in a second
+    # process while this one (the test runner, after the batch tests) was alive with
+    # cooperative launches of its own
+    rec = run_bench("--workload", "batch", "--advance-steps", "8", "--batch-per-phase")
+    assert rec["value"] > 0 and "per global phase" in rec["config"]["workload"]
 
 
 def test_bench_refuses_more_gpus():
