@@ -12,6 +12,8 @@
 // between phases: workgroup 0 clears the next phase's counter while the
 // current phase runs (nobody touches it then), and the grid barrier
 // publishes the clear.
+#include <algorithm>
+
 #include <hip/hip_cooperative_groups.h>
 #include <hip/hip_runtime.h>
 
@@ -104,9 +106,12 @@ __global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
 }
 
 // One global phase per launch: the same work with stream order in place of the
-// grid barrier, for processes that cannot make cooperative launches.
+// grid barrier, for processes that cannot make cooperative launches.  The
+// second bound (waves per SIMD) keeps two workgroups per compute unit: left
+// free, the compiler gives this kernel half again the registers of the
+// cooperative one and one workgroup per CU.
 template <typename T>
-__global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1))
+__global__ void __launch_bounds__(batch_wg(sizeof(T) == 8 ? 0 : 1), batch_wg(sizeof(T) == 8 ? 0 : 1) / 128)
     batch_phase_kernel(const PhaseArgs* __restrict__ probs, int count, int gp, long long n_steps, int* ctr)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -141,6 +146,16 @@ hipError_t launch_batch(int dtype, const PhaseArgs* d_args, int count, int nphas
 hipError_t launch_batch_phase(int dtype, const PhaseArgs* d_args, int count, int gp, long long n_steps, int grid,
                               size_t lds, hipStream_t st, int* ctr)
 {
+    // at most the workgroups this kernel keeps resident (grid is the cooperative kernel's);
+    // any grid covers the phase: grid-stride in phase 0, the counter after it
+    const void* f = dtype == 0 ? (const void*)batch_phase_kernel<double> : (const void*)batch_phase_kernel<float>;
+    int bpc = 0, dev = 0, cus = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&bpc, f, batch_wg(dtype), lds);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    if (bpc < 1) return hipErrorInvalidConfiguration;
+    grid = std::min(grid, bpc * cus);
     if (dtype == 0)
         hipLaunchKernelGGL(batch_phase_kernel<double>, dim3(grid), dim3(batch_wg(dtype)), lds, st, d_args, count, gp,
                            n_steps, ctr);
