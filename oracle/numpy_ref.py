@@ -59,25 +59,24 @@ def laplacian(T: np.ndarray) -> np.ndarray:
 
 
 def _pressure(Q, gm1):
-    inv = Q.dtype.type(1) / Q[0]
-    u = Q[1] * inv
-    v = Q[2] * inv
+    u = Q[1] / Q[0]
+    v = Q[2] / Q[0]
     return gm1 * (Q[3] - Q.dtype.type(0.5) * (Q[1] * u + Q[2] * v))
 
 
 def _phys_flux(Q, a, gamma, gm1):
     """Physical flux along the axis whose momentum is Q[a]; returns (F, |u_a| + c)."""
     b = 2 if a == 1 else 1
-    inv = Q.dtype.type(1) / Q[0]
-    ua = Q[a] * inv
-    ub = Q[b] * inv
+    rho = Q[0]
+    ua = Q[a] / rho
+    ub = Q[b] / rho
     p = gm1 * (Q[3] - Q.dtype.type(0.5) * (Q[a] * ua + Q[b] * ub))
     F = np.empty_like(Q)
     F[0] = Q[a]
     F[a] = Q[a] * ua + p
     F[b] = Q[a] * ub
     F[3] = (Q[3] + p) * ua
-    c = np.sqrt(gamma * p * inv)
+    c = np.sqrt(gamma * p / rho)
     return F, np.abs(ua) + c
 
 
@@ -86,11 +85,10 @@ def _roe_speed(L, R, a, gm1):
     b = 2 if a == 1 else 1
     t = L.dtype.type
     wl, wr = np.sqrt(L[0]), np.sqrt(R[0])
-    il, ir = t(1) / L[0], t(1) / R[0]
-    ual, ubl = L[a] * il, L[b] * il
-    uar, ubr = R[a] * ir, R[b] * ir
-    hl = (L[3] + _pressure(L, gm1)) * il
-    hr = (R[3] + _pressure(R, gm1)) * ir
+    ual, ubl = L[a] / L[0], L[b] / L[0]
+    uar, ubr = R[a] / R[0], R[b] / R[0]
+    hl = (L[3] + _pressure(L, gm1)) / L[0]
+    hr = (R[3] + _pressure(R, gm1)) / R[0]
     ua = (wl * ual + wr * uar) / (wl + wr)
     ub = (wl * ubl + wr * ubr) / (wl + wr)
     H = (wl * hl + wr * hr) / (wl + wr)
@@ -104,18 +102,16 @@ def _run_flux(A, B, C, D, a, gamma, scheme):
     t = B.dtype.type
     gm1 = gamma - t(1)
     pA, pB, pC, pD = (_pressure(X, gm1) for X in (A, B, C, D))
-    with np.errstate(divide="ignore", invalid="ignore"):
-        # 1/r_B and r_C through the shared 1/(pC - pB)
-        inv_d = t(1) / (pC - pB)
-        iB = (pB - pA) * inv_d
-        rC = (pD - pC) * inv_d
-        okB = (iB > 0) & (iB < np.inf)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        rB = (pC - pB) / (pB - pA)  # pressure ratio of the left cell
+        rC = (pD - pC) / (pC - pB)  # pressure ratio of the right cell
+        okB = (rB > 0) & (rB < np.inf)
         okC = (rC > 0) & (rC < np.inf)
         if scheme & 1:
-            phiL = t(0.5) * np.minimum(t(1) / iB, t(1))
+            phiL = t(0.5) * np.minimum(rB, t(1))
             phiR = t(0.5) * np.minimum(t(1) / rC, t(1))
         else:
-            phiL = t(0.5) * np.minimum(iB, t(1))
+            phiL = t(0.5) * np.minimum(t(1) / rB, t(1))
             phiR = t(0.5) * np.minimum(rC, t(1))
         L = np.where(okB[None], B + phiL[None] * (C - B), B)
         R = np.where(okC[None], C + phiR[None] * (B - C), C)

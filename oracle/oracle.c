@@ -231,32 +231,32 @@ static inline state4 load4(const REAL* Q, int64_t NN, int64_t k)
 }
 
 /* Equation of state (App. B): p = (gamma-1)(E - rho(u^2+v^2)/2), written
- * with the momenta: p = (gamma-1)(E - (m u + n v)/2); velocities as momentum
- * times 1/rho. */
+ * with the momenta and the velocities u = m/rho, v = n/rho:
+ * p = (gamma-1)(E - (m u + n v)/2). */
 static inline REAL pressure(state4 q, REAL gm1)
 {
-    const REAL inv = (REAL)1 / q.v[0];
-    const REAL u = q.v[1] * inv;
-    const REAL v = q.v[2] * inv;
+    const REAL u = q.v[1] / q.v[0];
+    const REAL v = q.v[2] / q.v[0];
     const REAL ke = q.v[1] * u + q.v[2] * v;
     return gm1 * (q.v[3] - (REAL)0.5 * ke);
 }
 
 /* Flux in the direction whose momentum is component a (a=1: x, F; a=2:
  * y, G) and the other momentum is component b; also the signal speed
- * |u_a| + c.  F = (m_a, m_a u_a + p, m_a u_b, (E+p) u_a). */
+ * |u_a| + c.  F = (m_a, m_a u_a + p, m_a u_b, (E+p) u_a), u_a = m_a/rho,
+ * c = sqrt(gamma p / rho). */
 static inline void phys_flux(state4 q, int a, int b, REAL gamma, REAL gm1, REAL f[4], REAL* speed)
 {
-    const REAL inv = (REAL)1 / q.v[0];
-    const REAL ua = q.v[a] * inv;
-    const REAL ub = q.v[b] * inv;
+    const REAL rho = q.v[0];
+    const REAL ua = q.v[a] / rho;
+    const REAL ub = q.v[b] / rho;
     const REAL ke = q.v[a] * ua + q.v[b] * ub;
     const REAL p = gm1 * (q.v[3] - (REAL)0.5 * ke);
     f[0] = q.v[a];
     f[a] = q.v[a] * ua + p;
     f[b] = q.v[a] * ub;
     f[3] = (q.v[3] + p) * ua;
-    const REAL c = (REAL)sqrt((double)(gamma * p * inv));
+    const REAL c = (REAL)sqrt((double)(gamma * p / rho));
     *speed = (REAL)fabs((double)ua) + c;
 }
 
@@ -282,11 +282,10 @@ static inline int ratio_ok(REAL r) { return r > (REAL)0 && r < (REAL)INFINITY; }
 static void roe_average(state4 L, state4 R, int a, int b, REAL gm1, REAL out[4])
 {
     const REAL wl = (REAL)sqrt((double)L.v[0]), wr = (REAL)sqrt((double)R.v[0]);
-    const REAL il = (REAL)1 / L.v[0], ir = (REAL)1 / R.v[0];
-    const REAL ual = L.v[a] * il, ubl = L.v[b] * il;
-    const REAL uar = R.v[a] * ir, ubr = R.v[b] * ir;
+    const REAL ual = L.v[a] / L.v[0], ubl = L.v[b] / L.v[0];
+    const REAL uar = R.v[a] / R.v[0], ubr = R.v[b] / R.v[0];
     const REAL pl = pressure(L, gm1), pr = pressure(R, gm1);
-    const REAL hl = (L.v[3] + pl) * il, hr = (R.v[3] + pr) * ir;
+    const REAL hl = (L.v[3] + pl) / L.v[0], hr = (R.v[3] + pr) / R.v[0];
     const REAL ua = (wl * ual + wr * uar) / (wl + wr);
     const REAL ub = (wl * ubl + wr * ubr) / (wl + wr);
     const REAL H = (wl * hl + wr * hr) / (wl + wr);
@@ -299,7 +298,10 @@ static void roe_average(state4 L, state4 R, int a, int b, REAL gm1, REAL out[4])
 
 /* Numerical flux through the face between cells B and C of the 1D run
  * A, B, C, D (App. B: pressure-ratio reconstruction, then the Rusanov-form
- * flux).  a selects the normal momentum component; scheme the variant bits. */
+ * flux).  a selects the normal momentum component; scheme the variant bits.
+ * Each cell's pressure ratio is the plain quotient of its forward and
+ * backward pressure jumps, and the minmod factor takes the plain reciprocal
+ * of that ratio. */
 static void face_flux_states(state4 A, state4 B, state4 C, state4 D, int a, REAL gamma, int scheme, REAL out[4],
                              state4* Lo, state4* Ro)
 {
@@ -307,16 +309,12 @@ static void face_flux_states(state4 A, state4 B, state4 C, state4 D, int a, REAL
     const int b = (a == 1) ? 2 : 1;
     const int literal = (scheme & SCHEME_LIMITER_LITERAL) != 0;
     const REAL pA = pressure(A, gm1), pB = pressure(B, gm1), pC = pressure(C, gm1), pD = pressure(D, gm1);
-    /* the ratios r_B = (pC-pB)/(pB-pA) and r_C = (pD-pC)/(pC-pB) through the
-     * shared jump: iB = 1/r_B = (pB-pA)/(pC-pB), r_C = (pD-pC)/(pC-pB), both
-     * as products with 1/(pC-pB); r_B is in (0, inf) exactly when iB is */
-    const REAL id = (REAL)1 / (pC - pB);
-    const REAL iB = (pB - pA) * id;
-    const REAL rC = (pD - pC) * id;
+    const REAL rB = (pC - pB) / (pB - pA); /* ratio at the left cell  */
+    const REAL rC = (pD - pC) / (pC - pB); /* ratio at the right cell */
     state4 L = B, R = C;
-    if (ratio_ok(iB)) {
+    if (ratio_ok(rB)) {
         /* minmod reading: min(1/r_B, 1); as printed: min(r_B, 1) */
-        const REAL e = literal ? (REAL)1 / iB : iB;
+        const REAL e = literal ? rB : (REAL)1 / rB;
         const REAL phi = (REAL)0.5 * (e < (REAL)1 ? e : (REAL)1);
         for (int c = 0; c < 4; ++c) L.v[c] = B.v[c] + phi * (C.v[c] - B.v[c]);
     }

@@ -167,6 +167,103 @@ def test_vortex_translates_at_45_degrees():
     assert min(orders) > 0.9, (errs, orders)
 
 
+def _density_wave_at_rest(n):
+    """Fluid at rest at constant pressure (E = 2.5, so p = 1) with a density wave that
+    depends on the integer cell index, so every density extremum sits on a cell centre and
+    no two neighbours are equal.  The momenta stay exactly zero and E exactly constant, so
+    every pressure jump is exactly zero, every pressure ratio is 0/0 and the spatial operator
+    is the first-order Rusanov form at every stage: the density diffuses with the speed
+    s = max(c_L, c_R) and only the time rule changes with dt."""
+    i = np.arange(n)
+    rho = 1 + 0.3 * np.cos(2 * np.pi * (i[None, :] - 3) / n) + 0.2 * np.cos(4 * np.pi * (i[:, None] - 5) / n)
+    return np.stack([rho, 0 * rho, 0 * rho, np.full_like(rho, 2.5)])
+
+
+def _time_self_convergence(run, n=32, t_end=1.0):
+    """Density at t_end from runs of 20, 40, 80 and 160 steps; returns the ratios of
+    successive differences (about 4 for a second-order time rule, 2 for a first-order one)."""
+    outs = [run(t_end / m, m) for m in (20, 40, 80, 160)]
+    d = [np.abs(outs[k][0] - outs[k + 1][0]).max() for k in range(3)]
+    assert np.all(outs[-1][1] == 0) and np.all(outs[-1][3] == outs[-1][3][0, 0])  # at rest, p constant
+    return [d[k] / d[k + 1] for k in range(2)]
+
+
+@pytest.mark.parametrize("impl", ["c", "numpy"])
+def test_rk2_is_second_order_in_time(impl):
+    """App. B time integration (explicit midpoint): with the spatial operator fixed (every
+    pressure ratio 0/0), successive halvings of dt shrink the differences about 4x."""
+    n = 32
+    dx = 10 / n
+    Q0 = _density_wave_at_rest(n)
+    run = oracle.euler_run if impl == "c" else numpy_ref.euler_run
+    ratios = _time_self_convergence(lambda dt, m: run(Q0, dt, dx, dx, GAMMA, m))
+    assert min(ratios) > 3.5, ratios
+
+
+def test_time_order_check_rejects_forward_euler_stages():
+    """Negative control: two forward-Euler half steps per step (a first-order rule built
+    from the twin's own stage) shrink the differences only 2x and fail the check above."""
+    n = 32
+    dx = 10 / n
+    Q0 = _density_wave_at_rest(n)
+
+    def fe_run(dt, m):
+        Q = Q0.copy()
+        h = 0.5 * dt / dx
+        for _ in range(m):
+            Qs = numpy_ref.euler_stage(Q, Q, h, h, np.float64(GAMMA))
+            Q = numpy_ref.euler_stage(Qs, Qs, h, h, np.float64(GAMMA))
+        return Q
+
+    ratios = _time_self_convergence(fe_run)
+    assert max(ratios) < 2.5, ratios
+
+
+def _velocities_by_reciprocal(monkeypatch):
+    """Plants, in the numpy twin only, the other rounding of the same equation of state and
+    flux: velocities as momentum times fl(1/rho) instead of the plain quotient m/rho."""
+
+    def pressure(Q, gm1):
+        inv = Q.dtype.type(1) / Q[0]
+        return gm1 * (Q[3] - Q.dtype.type(0.5) * (Q[1] * (Q[1] * inv) + Q[2] * (Q[2] * inv)))
+
+    def phys_flux(Q, a, gamma, gm1):
+        b = 2 if a == 1 else 1
+        inv = Q.dtype.type(1) / Q[0]
+        ua, ub = Q[a] * inv, Q[b] * inv
+        p = gm1 * (Q[3] - Q.dtype.type(0.5) * (Q[a] * ua + Q[b] * ub))
+        F = np.empty_like(Q)
+        F[0], F[a], F[b], F[3] = Q[a], Q[a] * ua + p, Q[a] * ub, (Q[3] + p) * ua
+        return F, np.abs(ua) + np.sqrt(gamma * p * inv)
+
+    monkeypatch.setattr(numpy_ref, "_pressure", pressure)
+    monkeypatch.setattr(numpy_ref, "_phys_flux", phys_flux)
+
+
+def test_pressure_rounding_flips_the_limiter_on_the_vortex_centre_lines(monkeypatch):
+    """The vortex's pressure is mirror-symmetric about x = 5 and y = 5, which are faces for
+    even N: across them the pressure jump is zero up to rounding, so its sign -- and with it
+    whether the limiter is on -- is decided by how p is rounded, and the face state moves by
+    half the momentum jump.  One step with velocities rounded as m*fl(1/rho) instead of m/rho
+    therefore moves the result by far more than the 1e-10 parity tolerance, and the largest
+    changes sit next to the centre lines.  Pins the plain quotients of the equation of state:
+    any re-rounding of the oracle fails this test."""
+    n = 256
+    dx = 10 / n
+    Q0 = problems.shu_vortex(n)
+    dt = oracle.cfl_dt(Q0, dx, dx, GAMMA, 0.4)
+    plain = oracle.euler_run(Q0, dt, dx, dx, GAMMA, 1)
+    assert np.array_equal(plain, numpy_ref.euler_run(Q0, dt, dx, dx, GAMMA, 1))
+    _velocities_by_reciprocal(monkeypatch)
+    other = numpy_ref.euler_run(Q0, dt, dx, dx, GAMMA, 1)
+    rel = np.abs(plain - other) / np.abs(plain).max(axis=(1, 2))[:, None, None]
+    assert rel.max() > 1e-6, rel.max()
+    centre = {n // 2 - 1, n // 2}
+    for k in range(4):
+        j, i = np.unravel_index(np.argmax(rel[k]), rel[k].shape)
+        assert j in centre or i in centre, (k, j, i)
+
+
 def test_cfl_uniform_closed_form():
     Q = problems.uniform_state(8, rho=1.0, u=1.0, v=1.0, p=1.0)
     c = math.sqrt(GAMMA)
