@@ -23,13 +23,11 @@ __device__ __forceinline__ T heat_update(T c, T xp, T xm, T yp, T ym, T r)
 // ---------------------------------------------------------------- Euler
 // State q = (rho, m = rho u, n = rho v, E).  Equation of state (App. B):
 // p = (gamma-1)(E - (m u + n v)/2).
-// Velocities are taken as momentum times 1/rho (one division per state).
 template <typename T>
 __device__ __forceinline__ T pressure(const T q[4], T gm1)
 {
-    const T inv = T(1) / q[0];
-    const T u = q[1] * inv;
-    const T v = q[2] * inv;
+    const T u = q[1] / q[0];
+    const T v = q[2] / q[0];
     const T ke = q[1] * u + q[2] * v;
     return gm1 * (q[3] - T(0.5) * ke);
 }
@@ -40,16 +38,16 @@ template <typename T, int A>
 __device__ __forceinline__ void phys_flux(const T q[4], T gamma, T gm1, T f[4], T& speed)
 {
     constexpr int Bc = (A == 1) ? 2 : 1;
-    const T inv = T(1) / q[0];
-    const T ua = q[A] * inv;
-    const T ub = q[Bc] * inv;
+    const T rho = q[0];
+    const T ua = q[A] / rho;
+    const T ub = q[Bc] / rho;
     const T ke = q[A] * ua + q[Bc] * ub;
     const T p = gm1 * (q[3] - T(0.5) * ke);
     f[0] = q[A];
     f[A] = q[A] * ua + p;
     f[Bc] = q[A] * ub;
     f[3] = (q[3] + p) * ua;
-    const T c = sqrt(gamma * p * inv);
+    const T c = sqrt(gamma * p / rho);
     speed = fabs(ua) + c;
 }
 
@@ -72,12 +70,11 @@ __device__ __forceinline__ T roe_speed(const T L[4], const T R[4], T gm1)
 {
     constexpr int Bc = (A == 1) ? 2 : 1;
     const T wl = sqrt(L[0]), wr = sqrt(R[0]);
-    const T il = T(1) / L[0], ir = T(1) / R[0];
-    const T ual = L[A] * il, ubl = L[Bc] * il;
-    const T uar = R[A] * ir, ubr = R[Bc] * ir;
+    const T ual = L[A] / L[0], ubl = L[Bc] / L[0];
+    const T uar = R[A] / R[0], ubr = R[Bc] / R[0];
     const T pl = gm1 * (L[3] - T(0.5) * (L[A] * ual + L[Bc] * ubl));
     const T pr = gm1 * (R[3] - T(0.5) * (R[A] * uar + R[Bc] * ubr));
-    const T hl = (L[3] + pl) * il, hr = (R[3] + pr) * ir;
+    const T hl = (L[3] + pl) / L[0], hr = (R[3] + pr) / R[0];
     const T den = wl + wr;
     const T ua = (wl * ual + wr * uar) / den;
     const T ub = (wl * ubl + wr * ubr) / den;
@@ -98,16 +95,12 @@ __device__ __forceinline__ void face_flux(const T qa[4], const T qb[4], const T 
                                           T pc, T pd, T gamma, T out[4])
 {
     const T gm1 = gamma - T(1);
-    // both face factors share the pressure jump across the face: with
-    // id = 1/(p_c - p_b), 1/r_b = (p_b - p_a) id and r_c = (p_d - p_c) id
-    // (r_b lies in (0, inf) exactly when 1/r_b does)
-    const T id = T(1) / (pc - pb);
-    const T ib = (pb - pa) * id;  // 1 / (ratio at the left cell)
-    const T rc = (pd - pc) * id;  // ratio at the right cell
+    const T rb = (pc - pb) / (pb - pa);  // ratio at the left cell
+    const T rc = (pd - pc) / (pc - pb);  // ratio at the right cell
     constexpr bool lit = (V & kLimiterLiteral) != 0;
     T L[4], R[4];
-    if (ratio_ok(ib)) {
-        const T f = lit ? T(1) / ib : ib;
+    if (ratio_ok(rb)) {
+        const T f = lit ? rb : T(1) / rb;
         const T phi = T(0.5) * (f < T(1) ? f : T(1));
 #pragma unroll
         for (int k = 0; k < 4; ++k) L[k] = qb[k] + phi * (qc[k] - qb[k]);
