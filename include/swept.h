@@ -187,6 +187,20 @@ int swept_conserved(swept_ctx* ctx, double* out);
 int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, void* d_work, size_t work_bytes,
                  void* hip_stream, double* dt_out);
 
+/* swept_cfl_dt without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and errors as swept_cfl_dt, bit for bit
+ * (the same kernels and reduction order); the 1024 partial maxima and the
+ * result live in a static device array of 8200 bytes inside the library,
+ * which holds one copy per GPU until the process ends and serves any grid
+ * the library accepts (nx <= 32768; larger grids are SWEPT_ESHAPE).  The
+ * array's device address is looked up on the first call on each device.
+ * All calls on one GPU share that array, so calls that overlap on one GPU
+ * (other threads, other streams) race; nothing in it needs clearing between
+ * calls.  Synchronises the stream; calls no allocating routine. */
+int swept_cfl_dt_noalloc(const swept_problem* prob, const void* d_state, double cfl, void* hip_stream,
+                         double* dt_out);
+
 /* ---- Adjoint of the swept heat advance (not in the paper) ------------------
  * For J(T^M) and g = dJ/dT^M, the discrete adjoint of n_steps heat steps
  * T^{m+1} = A T^m (A = I + r L) gives dJ/dT^0 = (A^T)^n g and

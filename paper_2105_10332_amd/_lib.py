@@ -61,6 +61,7 @@ _SIGS = {
     "swept_conserved": [_P, ctypes.POINTER(ctypes.c_double)],
     "swept_cfl_dt": [ctypes.POINTER(Problem), _P, ctypes.c_double, _P, ctypes.c_size_t, _P,
                      ctypes.POINTER(ctypes.c_double)],
+    "swept_cfl_dt_noalloc": [ctypes.POINTER(Problem), _P, ctypes.c_double, _P, ctypes.POINTER(ctypes.c_double)],
     "swept_destroy": [_P],
     "swept_tape_bytes": [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_size_t)],
     "swept_advance_checkpointed": [_P, ctypes.c_int64, _P, ctypes.c_size_t],
@@ -85,6 +86,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() (hipcc, gfx950)")
+        # PyTorch ships its own HIP runtime library; importing it first makes libswept bind to that
+        # same runtime, so the device pointers and streams torch hands over are valid here.  Loaded
+        # the other way round, the process holds two HIP runtimes and libswept's sees no device.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, args in _SIGS.items():
             f = getattr(L, name)

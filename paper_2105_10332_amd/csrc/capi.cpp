@@ -594,23 +594,22 @@ int swept_conserved(swept_ctx* c, double* out)
     return SWEPT_OK;
 }
 
-int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, void* d_work, size_t work_bytes,
-                 void* hip_stream, double* dt_out)
+// Validation shared by both CFL entry points (no HIP call).
+static int cfl_check(const swept_problem* prob, const void* d_state, double cfl, double* dt_out, swept_problem* q,
+                     Derived* d)
 {
-    if (!prob || !d_state || !d_work || !dt_out) return fail(SWEPT_EINVAL, "NULL argument");
+    if (!prob || !d_state || !dt_out) return fail(SWEPT_EINVAL, "NULL argument");
     if (prob->kind != SWEPT_EULER) return fail(SWEPT_ENOTSUP, "CFL time step is defined for Euler only");
     if (!(cfl > 0)) return fail(SWEPT_EINVAL, "cfl must be positive");
-    swept_problem q = *prob;
-    if (!(q.dt > 0)) q.dt = 1.0;  // dt is the output here; any positive value passes validation
-    Derived d;
-    const int rc = derive(&q, nullptr, &d);
-    if (rc) return rc;
-    const size_t need = workspace_for(d);
-    if (work_bytes < need) return fail(SWEPT_EWORKSPACE, "workspace %zu bytes < %zu needed", work_bytes, need);
-    char* w = static_cast<char*>(d_work);
-    double* partials = reinterpret_cast<double*>(w + align_up(d.state_bytes));
-    double* red = reinterpret_cast<double*>(w + align_up(d.state_bytes) + align_up(sizeof(double) * 4 * kParts));
-    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    *q = *prob;
+    if (!(q->dt > 0)) q->dt = 1.0;  // dt is the output here; any positive value passes validation
+    return derive(q, nullptr, d);
+}
+
+// The reduction itself: kParts partial maxima, then one fixed-order combine.
+static int cfl_run(const swept_problem& q, const Derived& d, const void* d_state, double cfl, double* partials,
+                   double* red, hipStream_t st, double* dt_out)
+{
     const size_t NN = (size_t)q.nx * q.ny;
     hipError_t e = swept::launch_cfl_max(q.dtype, d_state, NN, q.gamma, d.dx, d.dy, partials, kParts, red, st);
     if (e != hipSuccess) return hip_fail(e, "cfl reduction");
@@ -621,6 +620,36 @@ int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, voi
     if (!(smax > 0) || !std::isfinite(smax)) return fail(SWEPT_ENONFINITE, "max signal rate %g", smax);
     *dt_out = cfl / smax;
     return SWEPT_OK;
+}
+
+int swept_cfl_dt(const swept_problem* prob, const void* d_state, double cfl, void* d_work, size_t work_bytes,
+                 void* hip_stream, double* dt_out)
+{
+    if (!d_work) return fail(SWEPT_EINVAL, "NULL argument");
+    swept_problem q;
+    Derived d;
+    const int rc = cfl_check(prob, d_state, cfl, dt_out, &q, &d);
+    if (rc) return rc;
+    const size_t need = workspace_for(d);
+    if (work_bytes < need) return fail(SWEPT_EWORKSPACE, "workspace %zu bytes < %zu needed", work_bytes, need);
+    char* w = static_cast<char*>(d_work);
+    double* partials = reinterpret_cast<double*>(w + align_up(d.state_bytes));
+    double* red = reinterpret_cast<double*>(w + align_up(d.state_bytes) + align_up(sizeof(double) * 4 * kParts));
+    return cfl_run(q, d, d_state, cfl, partials, red, reinterpret_cast<hipStream_t>(hip_stream), dt_out);
+}
+
+int swept_cfl_dt_noalloc(const swept_problem* prob, const void* d_state, double cfl, void* hip_stream,
+                         double* dt_out)
+{
+    static_assert(swept::kNoAllocParts == kParts, "the static scratch holds exactly the reduction's partials");
+    swept_problem q;
+    Derived d;
+    const int rc = cfl_check(prob, d_state, cfl, dt_out, &q, &d);  // rejects nx > 32768 (the scratch's limit)
+    if (rc) return rc;
+    double* scratch = nullptr;
+    const hipError_t e = swept::noalloc_scratch(&scratch);
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    return cfl_run(q, d, d_state, cfl, scratch, scratch + kParts, reinterpret_cast<hipStream_t>(hip_stream), dt_out);
 }
 
 int swept_destroy(swept_ctx* c)

@@ -24,6 +24,8 @@
 //      cell's top two levels, exactly the values later shapes read.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_common.h"
 
 namespace swept {
@@ -401,6 +403,32 @@ hipError_t launch_cfl_max(int dtype, const void* q, size_t NN, double gamma, dou
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(combine_partials, dim3(1), dim3(256), 0, st, partials, nparts, 1, out);
     return hipGetLastError();
+}
+
+// ------------------------------------------------- allocation-free scratch
+// Partials and result of the CFL max-reduction of swept_cfl_dt_noalloc: a
+// file-scope device array (each GPU holds its own copy until the process
+// ends).  In host code its name is only a stand-in, so the device address is
+// looked up once per device and kept; kernels get that address.
+static __device__ __align__(256) double scratch[kNoAllocParts + 1];
+
+hipError_t noalloc_scratch(double** out)
+{
+    static std::mutex mu;
+    static double* ptr[kNoAllocMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kNoAllocMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = static_cast<double*>(p);
+    }
+    *out = ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace swept

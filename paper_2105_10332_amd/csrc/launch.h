@@ -97,6 +97,12 @@ hipError_t launch_batch_phase(int dtype, const PhaseArgs* d_args, int count, int
 hipError_t launch_combine(const double* partials, int nparts, double* out, hipStream_t st);
 hipError_t launch_plane_sums(int dtype, const void* x, int nvar, size_t NN, double* partials, int nparts,
                              double* out, hipStream_t st);
+// Scratch of the allocation-free CFL entry point: kNoAllocParts partial maxima
+// and one result, in a file-scope device array; *out = its address on the
+// current device (looked up once per device).
+constexpr int kNoAllocParts = 1024;
+constexpr int kNoAllocMaxDevices = 64;
+hipError_t noalloc_scratch(double** out);
 hipError_t launch_cfl_max(int dtype, const void* q, size_t NN, double gamma, double dx, double dy, double* partials,
                           int nparts, double* out, hipStream_t st);
 

@@ -233,6 +233,16 @@ def swept_cfl_dt(state: torch.Tensor, length: float, cfl: float, gamma: float = 
     return out.value
 
 
-__all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_workspace_bytes", "make_problem", "HEAT",
+def swept_cfl_dt_noalloc(state: torch.Tensor, length: float, cfl: float, gamma: float = 1.4) -> float:
+    """swept_cfl_dt with the library's static device scratch: no workspace, no allocation."""
+    n = state.shape[-1]
+    prob = make_problem(EULER, n, state.dtype, 1.0, length, gamma=gamma)
+    out = ctypes.c_double(0.0)
+    check(lib().swept_cfl_dt_noalloc(ctypes.byref(prob), _dev_ptr(state), float(cfl), _stream_ptr(),
+                                     ctypes.byref(out)))
+    return out.value
+
+
+__all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_cfl_dt_noalloc", "swept_workspace_bytes", "make_problem", "HEAT",
            "EULER", "LIMITER_LITERAL", "SPEED_ROE", "BC_PERIODIC", "BC_DIRICHLET", "BC_NEUMANN",
            "BC_REFLECT", "BATCH_COOPERATIVE", "BATCH_PER_PHASE", "_lib"]
