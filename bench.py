@@ -20,7 +20,8 @@ step), adjoint (1024^2 FP32 heat, 2000 steps: forward with checkpoints +
 reverse sweep per step), batch (48 heat + 16 Euler problems, FP32, 200 steps,
 one persistent launch per step), study (the paper's parameter study at a
 GPU share of 100%: speedup over array sizes 320-1120 and block sizes 8-32), graphs
-(eager launches against replayed HIP graphs at 320^2 and 1024^2).
+(eager launches against replayed HIP graphs at 320^2 and 1024^2), hetero (the advance split
+between the GPU and the host cores at GPU shares 0-100%, Eq. 2).
 
 Usage: python bench.py [--steps K] [--warmup W] [--dtype f64|f32] [--tile B] [--workload W]
 """
@@ -88,7 +89,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["heat", "euler", "adjoint", "batch", "study", "graphs"], default="heat")
+    ap.add_argument("--workload", choices=["heat", "euler", "adjoint", "batch", "study", "graphs", "hetero"],
+                    default="heat")
+    ap.add_argument("--threads", type=int, default=0, help="hetero workload: host worker threads (0: default)")
     ap.add_argument("--dtype", choices=["f64", "f32"], default=None)
     ap.add_argument("--tile", type=int, default=0, help="0: tuned or default tile")
     ap.add_argument("--wg", type=int, default=0, help="0: tuned or library default")
@@ -183,7 +186,10 @@ def roofline(plan, S, nvar, launches, sec, kernel):
     avg = sec / launches
     ach = alg / avg / 1e9
     return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": None, "kernel": kernel, "alg_bytes_per_launch": alg, "avg_launch_us": avg * 1e6}
+            "traffic": None, "kernel": kernel, "alg_bytes_per_launch": alg, "avg_launch_us": avg * 1e6,
+            "clock": "HIP events recorded on the launch stream around the timed advances, divided by the "
+                     "phase launches they hold (the rocprofv3 kernel-trace average of the same command is "
+                     "in profiles/)"}
 
 
 # Per-update costs of the swept heat kernel beside its HBM bytes, for the bound
@@ -432,16 +438,94 @@ def run_batch(args):
             sv.swept_advance(M)
 
     ssec, _ = timed(seq, 1)
+    # explicit teardown: finish the stream and release the batch, the solvers and their device
+    # memory before the process exits
+    torch.cuda.synchronize()
+    grid = b.grid
+    b.close()
+    for sv in solvers:
+        sv.close()
+    del solvers, b, items, init
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     cfg = {"workload": f"batch of 48 heat (edges 128-1024, r 0.05-0.24) + 16 Euler vortex (edges 256-1024, "
                        f"eps 1-5) problems, {M} steps each, "
                        f"{'one launch per global phase' if args.batch_per_phase else 'one persistent launch'}; "
-                       f"grid {b.grid} workgroups",
-           "problems": len(items), "grid": b.grid,
+                       f"grid {grid} workgroups",
+           "problems": len(ens), "grid": grid,
            "tiles": {"heat": sorted(set(t for it, t in zip(ens, tiles) if it.kind == "heat")),
                      "euler": sorted(set(t for it, t in zip(ens, tiles) if it.kind == "euler"))}}
     out = base_record(args, cells * args.steps / sec, "cell-updates/s", sec, dt_name, cfg)
     out["sequential_swept"] = {"value": cells / ssec, "unit": "cell-updates/s", "ms": ssec * 1e3}
     out["wall_s"] = wall
+    return out
+
+
+HETERO_SHARES = tuple(k / 10 for k in range(11))  # GPU shares 0 %, 10 %, ..., 100 % (Sec. 4)
+
+
+def run_hetero(args):
+    """The paper's GPU share (Eq. 2, Sec. 4): the swept advance split between the GPU (tile rows
+    below the share) and the host cores, shares 0 ... 100 % in 10 % steps.  Heat FP64 (r = 0.2,
+    16 Fourier modes) on the paper's array sizes (500 steps, tile 32) and on the 4096^2 grid of the
+    default workload (tile 64, --advance-steps steps, default 100); Euler FP64 (vortex, CFL 0.4,
+    tile 16, 500 steps) on the two smallest sizes.  Each (grid, share) is timed over one advance
+    after a warm advance; every result is checked bit for bit against the all-GPU advance."""
+    import numpy as np
+    import torch
+
+    from paper_2105_10332_amd import problems
+    from paper_2105_10332_amd.solver import EULER, HEAT, SweptHetero, SweptSolver, swept_cfl_dt
+
+    cases = [("heat", n, 32, 500) for n in STUDY_SIZES] + [("heat", 4096, 64, args.advance_steps or 100)]
+    cases += [("euler", n, 16, 500) for n in STUDY_SIZES[:2]]
+    table, t_all, threads = {}, time.perf_counter(), None
+    for kind, n, tile, M in cases:
+        if kind == "heat":
+            x0 = torch.tensor(problems.heat_fourier_modes(n), device="cuda")
+            code, dt, L = HEAT, 0.2 / n / n, 1.0
+        else:
+            x0 = torch.tensor(problems.shu_vortex(n), device="cuda")
+            code, dt, L = EULER, swept_cfl_dt(x0, 10.0, 0.4), 10.0
+        x = x0.clone()
+        sv = SweptSolver(code, x, dt=dt, length=L, alpha=1.0, gamma=1.4, tile=tile)
+        sv.swept_advance(M)
+        x.copy_(x0)
+        ref_sec, _ = timed(lambda: sv.swept_advance(M), 1)
+        ref = x.clone()
+        row = {}
+        for share in HETERO_SHARES:
+            h = SweptHetero(sv, share, args.threads)
+            threads = h.query()[2]
+            x.copy_(x0)
+            h.swept_hetero_advance(min(M, 2 * tile))  # warm: pinned buffers and worker threads
+            x.copy_(x0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            h.swept_hetero_advance(M)
+            el = time.perf_counter() - t
+            g, c, _ = h.query()
+            h.close()
+            if not torch.equal(x, ref):
+                raise RuntimeError(f"{kind} {n} share {share}: result differs from the all-GPU advance")
+            row[f"{share:.1f}"] = {"ms": el * 1e3, "gpu_rows": g, "cpu_rows": c}
+        sv.close()
+        best = min(row, key=lambda k: row[k]["ms"])
+        table[f"{kind} {n}"] = {"tile": tile, "steps": M, "all_gpu_swept_ms": ref_sec * 1e3, "by_share": row,
+                                "fastest_share": best}
+        print(f"hetero {kind} {n}: " + ", ".join(f"{k}:{v['ms']:.1f}" for k, v in row.items()), file=sys.stderr,
+              flush=True)
+    cfg = {"workload": "GPU share of the swept advance (Eq. 2), 0-100% in 10% steps: heat FP64 r=0.2 on "
+                       f"{list(STUDY_SIZES)} (500 steps, tile 32) and 4096^2 (tile 64), Euler FP64 vortex on "
+                       f"{list(STUDY_SIZES[:2])} (500 steps, tile 16); host worker threads {threads}",
+           "shares": list(HETERO_SHARES)}
+    c2 = table["heat 4096"]
+    out = base_record(args, c2["all_gpu_swept_ms"] / c2["by_share"]["0.9"]["ms"],
+                      "x (all-GPU swept time / time at a GPU share of 90%, heat 4096^2)",
+                      time.perf_counter() - t_all, "f64", cfg)
+    out["ms_per_step"] = None
+    out["table"] = table
+    out["host_threads"] = threads
     return out
 
 
@@ -595,7 +679,7 @@ def main():
         copy_reference()
         return
     fn = {"heat": run_heat, "euler": run_euler, "adjoint": run_adjoint, "batch": run_batch,
-          "study": run_study, "graphs": run_graphs}[args.workload]
+          "study": run_study, "graphs": run_graphs, "hetero": run_hetero}[args.workload]
     print(json.dumps(fn(args)), flush=True)
 
 

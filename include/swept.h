@@ -272,6 +272,35 @@ int swept_batch_grid(const swept_batch* ctx, int32_t* grid);
 int swept_batch_set_stream(swept_batch* ctx, void* hip_stream);
 int swept_batch_destroy(swept_batch* ctx);
 
+/* ---- Heterogeneous share: GPU and host cores together (Sec. 3.2, Eq. 2) ----
+ * The paper divides the work of every phase between GPU and CPU by a GPU
+ * share s = G/W of the blocks.  Here the tile rows jy < G = floor(s T + 1/2)
+ * (T = nx/tile rows of tiles) run on the GPU, as one launch of the phase
+ * kernel restricted to those rows, while host worker threads run the shape
+ * instances of the other rows at the same time, each on the same memory
+ * protocol and per-cell arithmetic (so the result equals swept_advance bit
+ * for bit for every s).  After every phase the two sides exchange the rows
+ * within tile of the two split lines (the GPU's copy of those rows is fetched
+ * into pinned host memory, merged with the cells the host wrote, and sent
+ * back); at the end the host's rows of the final level go to the GPU.  The
+ * paper splits along x; this layout is x-fastest, so the split runs along y,
+ * where each exchanged band is contiguous (the problems and the
+ * decomposition are symmetric in x and y).  Periodic problems, heat and
+ * Euler (every scheme variant); SWEPT_ENOTSUP for walls.
+ *
+ * swept_hetero_init binds to ctx (which must outlive it; no other call may
+ * run on ctx concurrently) and holds pinned host memory of two state copies
+ * plus the exchange band (no device memory).  cpu_threads = 0 takes
+ * OMP_NUM_THREADS, else the host's hardware threads.  gpu_share in [0, 1]:
+ * 1 is the all-GPU swept_advance, 0 runs every instance on the host.
+ * swept_hetero_advance runs on ctx's stream and synchronises it. */
+typedef struct swept_hetero swept_hetero;
+int swept_hetero_init(swept_hetero** h, swept_ctx* ctx, double gpu_share, int32_t cpu_threads);
+int swept_hetero_advance(swept_hetero* h, int64_t n_steps);
+/* Tile rows on each side and the host worker threads. */
+int swept_hetero_query(const swept_hetero* h, int32_t* gpu_rows, int32_t* cpu_rows, int32_t* threads);
+int swept_hetero_destroy(swept_hetero* h);
+
 /* Message for the last error on this thread ("" if none). */
 const char* swept_last_error(void);
 

@@ -76,6 +76,11 @@ _SIGS = {
     "swept_batch_set_mode": [_P, ctypes.c_int32],
     "swept_batch_set_stream": [_P, _P],
     "swept_batch_destroy": [_P],
+    "swept_hetero_init": [ctypes.POINTER(_P), _P, ctypes.c_double, ctypes.c_int32],
+    "swept_hetero_advance": [_P, ctypes.c_int64],
+    "swept_hetero_query": [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                           ctypes.POINTER(ctypes.c_int32)],
+    "swept_hetero_destroy": [_P],
 }
 
 _lib = None

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libswept.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "batch.hip", "capi.cpp"]
+SOURCES = ["kernels.hip", "adjoint.hip", "batch.hip", "capi.cpp", "hetero.cpp"]
 ARCH = os.environ.get("SWEPT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -8,11 +8,14 @@
 #include <cstdarg>
 #include <cstdio>
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "../../include/swept.h"
+#include "hetero.h"
 #include "launch.h"
 
 namespace {
@@ -47,7 +50,7 @@ struct Derived {
 };
 
 // LDS of one swept workgroup: heat keeps two level-parity windows; Euler
-// also a pressure plane and a face-flux buffer (kernels.hip, euler_level).
+// also a pressure plane (kernels.hip, euler_level).
 size_t phase_lds(int nvar, int n, int tile, size_t scalar)
 {
     if (nvar == 1) {
@@ -886,6 +889,110 @@ int swept_batch_set_stream(swept_batch* b, void* hip_stream)
 int swept_batch_destroy(swept_batch* b)
 {
     delete b;
+    return SWEPT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- heterogeneous share
+
+struct swept_hetero {
+    swept_ctx* ctx = nullptr;
+    swept::Hetero* run = nullptr;
+    int gpu_rows = 0, cpu_rows = 0, threads = 0;
+};
+
+extern "C" {
+
+int swept_hetero_init(swept_hetero** out, swept_ctx* c, double gpu_share, int32_t cpu_threads)
+{
+    if (!out) return fail(SWEPT_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!c) return fail(SWEPT_EINVAL, "ctx is NULL");
+    if (!(gpu_share >= 0.0 && gpu_share <= 1.0)) return fail(SWEPT_EINVAL, "gpu_share=%g outside [0, 1]", gpu_share);
+    if (cpu_threads < 0 || cpu_threads > 1024) return fail(SWEPT_EINVAL, "cpu_threads=%d outside [0, 1024]", cpu_threads);
+    if (c->prob.boundary != SWEPT_BC_PERIODIC)
+        return fail(SWEPT_ENOTSUP, "the heterogeneous advance runs periodic problems only");
+    const int tiles = c->prob.nx / c->d.tile;
+    int threads = cpu_threads;
+    if (threads == 0) {
+        const char* env = std::getenv("OMP_NUM_THREADS");
+        threads = env ? std::atoi(env) : 0;
+        if (threads <= 0) threads = (int)std::thread::hardware_concurrency();
+        if (threads <= 0) threads = 1;
+        threads = std::min(threads, 256);
+    }
+    swept_hetero* h = new (std::nothrow) swept_hetero();
+    if (!h) return fail(SWEPT_EINVAL, "out of host memory");
+    h->ctx = c;
+    h->gpu_rows = (int)std::floor(gpu_share * tiles + 0.5);  // Eq. 2: G = s W, in whole tile rows
+    h->cpu_rows = tiles - h->gpu_rows;
+    h->threads = threads;
+    swept::HeteroSetup s;
+    s.kind = c->prob.kind;
+    s.dtype = c->prob.dtype;
+    s.scheme = c->prob.scheme;
+    s.N = c->prob.nx;
+    s.b = c->d.tile;
+    s.h = c->d.h;
+    s.tiles = tiles;
+    s.nvar = c->d.nvar;
+    s.lps = c->d.lps;
+    s.wg = c->d.wg;
+    s.lds = c->d.lds_bytes;
+    s.state_bytes = c->d.state_bytes;
+    try {
+        s.tab.resize(swept::level_table_entries(c->d.h));
+    } catch (...) {
+        delete h;
+        return fail(SWEPT_EINVAL, "out of host memory");
+    }
+    build_level_table(c->d, s.tab.data());
+    s.base = phase_args(c, 0);
+    s.d0 = c->state;
+    s.d1 = c->buf1;
+    s.stream = c->stream;
+    s.gpu_rows = h->gpu_rows;
+    s.threads = threads;
+    const hipError_t e = swept::hetero_create(s, &h->run);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "heterogeneous runner (pinned host buffers)");
+    }
+    *out = h;
+    return SWEPT_OK;
+}
+
+int swept_hetero_advance(swept_hetero* h, int64_t n_steps)
+{
+    if (!h) return fail(SWEPT_EINVAL, "ctx is NULL");
+    if (n_steps < 0) return fail(SWEPT_EINVAL, "n_steps=%lld < 0", (long long)n_steps);
+    if (n_steps * h->ctx->d.lps > (int64_t)1 << 30) return fail(SWEPT_EINVAL, "n_steps too large");
+    if (n_steps == 0) return SWEPT_OK;
+    if (h->cpu_rows == 0) {  // share 1: the all-GPU advance
+        const int rc = advance_impl(h->ctx, n_steps);
+        if (rc) return rc;
+        const hipError_t e = hipStreamSynchronize(h->ctx->stream);
+        return e == hipSuccess ? SWEPT_OK : hip_fail(e, "hipStreamSynchronize");
+    }
+    const hipError_t e = swept::hetero_advance(h->run, (long long)n_steps, h->ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "heterogeneous advance");
+    return SWEPT_OK;
+}
+
+int swept_hetero_query(const swept_hetero* h, int32_t* gpu_rows, int32_t* cpu_rows, int32_t* threads)
+{
+    if (!h || !gpu_rows || !cpu_rows || !threads) return fail(SWEPT_EINVAL, "NULL argument");
+    *gpu_rows = h->gpu_rows;
+    *cpu_rows = h->cpu_rows;
+    *threads = h->threads;
+    return SWEPT_OK;
+}
+
+int swept_hetero_destroy(swept_hetero* h)
+{
+    if (h) swept::hetero_destroy(h->run);
+    delete h;
     return SWEPT_OK;
 }
 

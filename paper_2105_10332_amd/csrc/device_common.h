@@ -17,7 +17,7 @@ namespace swept {
 // kernels use i < 2^15 and d < 150: window cells, thread indices, widths).
 __device__ __forceinline__ int qdiv(int i, float inv) { return (int)(((float)i + 0.5f) * inv); }
 
-__device__ __forceinline__ int wrapi(int g, int N)
+__host__ __device__ __forceinline__ int wrapi(int g, int N)
 {
     g += (g < 0) ? N : 0;
     g -= (g >= N) ? N : 0;
@@ -87,7 +87,7 @@ __device__ __forceinline__ void wall_face(const T* __restrict__ prev, const T* _
     face_flux<T, A, V>(q[0], q[1], q[2], q[3], p[0], p[1], p[2], p[3], gamma, out);
 }
 
-__device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
+__host__ __device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
 {
     const int t = lvl - (w - 1) * h;
     if (lvl < 1 || t < 1 || t > 2 * h - 1) return 0;
@@ -115,7 +115,7 @@ __device__ __forceinline__ int half_width(int w, int lvl, int h, int n)
 constexpr int RING_LEVEL0 = 4, RING_Q0 = 8, RING_Q1 = 16;
 
 template <int R, int TWO_STAGE>
-__device__ __forceinline__ int ring_parities(int wx, int wy, int lo, int hi, int h, int b, int C, int lx, int ly,
+__host__ __device__ __forceinline__ int ring_parities(int wx, int wy, int lo, int hi, int h, int b, int C, int lx, int ly,
                                              bool owner_q = false)
 {
     const int ax = lx >= C ? lx - C : C - 1 - lx;
@@ -170,13 +170,21 @@ struct RingSrc {
 
 // Up-front load of every ring of the shape: a strided pass over the W x W
 // window (LDS row pitch PITCH), KB cells per thread per batch with all their
-// loads issued before any LDS write, so the batch costs one memory latency.
-template <class S, typename T>
+// loads issued before any LDS write, so the batch costs one memory latency
+// (two cells per batch for the FP64 Euler state, whose 2 x 4 values per cell
+// would otherwise hold 64 registers).  WRAP = false when the window stays
+// inside the domain (no periodic wrap of the global index).
+//
+// Euler (NVAR = 4) also writes the pressure of every loaded value into the
+// pressure plane of its level parity (LDS after the two state buffers), so
+// that no level recomputes the pressures of its ring.
+template <class S, typename T, bool WRAP = true>
 __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>& src, int W, int P, int PITCH, int N,
                                               size_t NN,
-                                              int ox, int oy, int wx, int wy, int lo, int hi, int h, int C)
+                                              int ox, int oy, int wx, int wy, int lo, int hi, int h, int C,
+                                              T gm1 = T(0))
 {
-    constexpr int NVAR = S::NVAR, KB = 4;
+    constexpr int NVAR = S::NVAR, KB = (NVAR * sizeof(T) >= 32) ? 2 : 4;
     const T* __restrict__ g0 = src.g0;
     const T* __restrict__ g1 = src.g1;
     const T* __restrict__ z0 = src.lvl0;
@@ -198,7 +206,8 @@ __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>&
                 li[k] = ly * PITCH + lx;
                 pm[k] = ring_parities<S::R, S::TWO_STAGE>(wx, wy, lo, hi, h, W - 2 * S::R, C, lx, ly, owner_q);
                 if (pm[k] & 3) {
-                    const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
+                    const size_t gi = WRAP ? (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N)
+                                           : (size_t)(oy + ly) * N + (ox + lx);
                     if (pm[k] & 1) {
                         if (pm[k] & RING_LEVEL0) {
 #pragma unroll
@@ -227,49 +236,73 @@ __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>&
         for (int k = 0; k < KB; ++k)
 #pragma unroll
             for (int p = 0; p < 2; ++p)
-                if (pm[k] & (1 << p))
+                if (pm[k] & (1 << p)) {
 #pragma unroll
                     for (int c = 0; c < NVAR; ++c) lds[p * BUF + c * P + li[k]] = v[k][p][c];
+                    if constexpr (NVAR == 4) lds[2 * BUF + p * P + li[k]] = pressure(v[k][p], gm1);
+                }
     }
 }
 
+// Value of the next lane (lane + 1) of the wavefront: a DPP wavefront shift
+// (wave_shl:1, lane i reads lane i+1), one VALU move per 32 bits.  Lane 63
+// gets 0; the face passes never use that lane's result.
+__device__ __forceinline__ int next_lane_b32(int v) { return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false); }
+__device__ __forceinline__ float next_lane(float v) { return __int_as_float(next_lane_b32(__float_as_int(v))); }
+__device__ __forceinline__ double next_lane(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned lo = (unsigned)next_lane_b32((int)(unsigned)b);
+    const unsigned hi = (unsigned)next_lane_b32((int)(unsigned)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// One Euler stage-level on the footprint [x0, x0+fw) x [y0, y0+fh) of the
+// window (LDS row pitch PW, plane stride P): Q^l = base - cx dF - cy dG with
+// base = Q^{l-1} (first RK stage) or Q^{l-2} held in cur (second stage),
+// evaluated as (base - cx (F+ - F-)) - cy (G+ - G-) -- the oracle's order.
+// pprev holds the pressures of the Q^{l-1} values in prev (every cell of the
+// footprint grown by 2, the four-cell runs); PNEXT: pcur receives the
+// pressure of each finished cell, for the next level.
+//   X: face fluxes and the x update, row by row.  A row of fw cells has fw+1
+//      faces; the items (row, face) are numbered row by row and each
+//      wavefront takes 64 consecutive items starting 63 after the previous
+//      one, so the face right of every updated cell is the next lane's face
+//      (one shuffle per value) and the wave's last lane only computes the
+//      face the lane before it needs.  No face buffer, no barrier between the
+//      fluxes and the update.
+//   Y: the same column by column, then the finished cell goes to cur (and its
+//      pressure to pcur) and to the store policy.
+// Lanes past the last item compute a copy of the last item's face so that
+// every lane takes part in the shuffle; their results are dropped.
 // BC != 0: walls (see wall_cell); ex, ey are the window-local indices of the
 // domain's first column and row (window_edge).  A face at the edge itself
-// exists once per side: the face buffer keeps the lower side's flux, and the
+// exists once per side: the pass computes the lower side's flux, and the
 // first cell past the edge recomputes its own.
-template <typename T, int V, class Store, int BC = 0>
-__device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, T* __restrict__ pbuf,
-                                            T* __restrict__ fbuf, int FS, int W, int P, int x0, int y0, int fw, int fh,
+template <typename T, int V, class Store, int BC = 0, bool PNEXT = true>
+__device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, const T* __restrict__ pbuf,
+                                            T* __restrict__ pcur, int PW, int P, int x0, int y0, int fw, int fh,
                                             bool second_stage, T gamma, T cx, T cy, const Store& store, int ex = 0,
                                             int ey = 0)
 {
     const int nthr = blockDim.x, tid = threadIdx.x;
+    const int lane = tid & 63, slots = nthr >> 6;
     const T gm1 = gamma - T(1);
-    {  // A: pressures on [x0-2, x0+fw+2) x [y0-2, y0+fh+2)
-        const int bw = fw + 4, cnt = bw * (fh + 4);
-        const float inv = 1.0f / (float)bw;
-        for (int i = tid; i < cnt; i += nthr) {
-            const int q = qdiv(i, inv);
-            const int li = (y0 - 2 + q) * W + (x0 - 2 + (i - q * bw));
-            T s4[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) s4[c] = prev[c * P + li];
-            pbuf[li] = pressure(s4, gm1);
-        }
-    }
-    __syncthreads();
-    {  // B1: x faces between cells x0-1+k and x0+k, k = 0..fw, rows y0..y0+fh-1
+    {  // X: faces between cells x0-1+k and x0+k of row y0+q (k = 0..fw), then the x update of cell x0+k
         const int nf = fw + 1, cnt = nf * fh;
         const float inv = 1.0f / (float)nf;
-        for (int i = tid; i < cnt; i += nthr) {
-            const int q = qdiv(i, inv);
-            const int k = i - q * nf;
-            const int lb = (y0 + q) * W + (x0 - 1 + k);
-            T qa[4], qb[4], qc[4], qd[4], f[4];
+        for (int s = tid >> 6; 63 * s <= cnt - 2; s += slots) {
+            const int i = 63 * s + lane;
+            const int ic = i < cnt ? i : cnt - 1;
+            const int q = qdiv(ic, inv);
+            const int k = ic - q * nf;
             const int a = x0 - 1 + k;
+            const int lb = (y0 + q) * PW + a;
+            T f[4];
             if (BC != 0 && a - 1 < ex && a + 2 >= ex) {
-                wall_face<T, 1, V, BC>(prev, pbuf, W, P, (y0 + q) * W, a, ex, a < ex, gamma, f);
+                wall_face<T, 1, V, BC>(prev, pbuf, PW, P, (y0 + q) * PW, a, ex, a < ex, gamma, f);
             } else {
+                T qa[4], qb[4], qc[4], qd[4];
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
                     qa[c] = prev[c * P + lb - 1];
@@ -279,85 +312,74 @@ __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, 
                 }
                 face_flux<T, 1, V>(qa, qb, qc, qd, pbuf[lb - 1], pbuf[lb], pbuf[lb + 1], pbuf[lb + 2], gamma, f);
             }
+            T fr[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) fbuf[c * FS + i] = f[c];
-        }
-    }
-    __syncthreads();
-    const int cells = fw * fh;
-    const float inv_fw = 1.0f / (float)fw;
-    {  // C1: x update
-        const int nf = fw + 1;
-        for (int i = tid; i < cells; i += nthr) {
-            const int q = qdiv(i, inv_fw);
-            const int k = i - q * fw;
-            const int li = (y0 + q) * W + (x0 + k);
-            const int fi = q * nf + k;  // face i-1/2; face i+1/2 is fi + 1
-            T fl[4];
-#pragma unroll
-            for (int c = 0; c < 4; ++c) fl[c] = fbuf[c * FS + fi];
-            if (BC != 0 && x0 + k == ex)  // the wall face as seen from this side
-                wall_face<T, 1, V, BC>(prev, pbuf, W, P, (y0 + q) * W, ex - 1, ex, false, gamma, fl);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const T base = second_stage ? cur[c * P + li] : prev[c * P + li];
-                const T dF = fbuf[c * FS + fi + 1] - fl[c];
-                cur[c * P + li] = base - cx * dF;
-            }
-        }
-    }
-    __syncthreads();
-    {  // B2: y faces between rows y0-1+k and y0+k, k = 0..fh, columns x0..x0+fw-1
-        const int cnt = fw * (fh + 1);
-        for (int i = tid; i < cnt; i += nthr) {
-            const int k = qdiv(i, inv_fw);
-            const int xo = i - k * fw;
-            const int lb = (y0 - 1 + k) * W + (x0 + xo);
-            T qa[4], qb[4], qc[4], qd[4], f[4];
-            const int a = y0 - 1 + k;
-            if (BC != 0 && a - 1 < ey && a + 2 >= ey) {
-                wall_face<T, 2, V, BC>(prev, pbuf, W, P, x0 + xo, a, ey, a < ey, gamma, f);
-            } else {
+            for (int c = 0; c < 4; ++c) fr[c] = next_lane(f[c]);
+            if (i < cnt && lane < 63 && k < fw) {
+                const int li = lb + 1;  // cell x0+k: face f on its left, fr on its right
+                if (BC != 0 && x0 + k == ex)  // the wall face as seen from this side
+                    wall_face<T, 1, V, BC>(prev, pbuf, PW, P, (y0 + q) * PW, ex - 1, ex, false, gamma, f);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    qa[c] = prev[c * P + lb - W];
-                    qb[c] = prev[c * P + lb];
-                    qc[c] = prev[c * P + lb + W];
-                    qd[c] = prev[c * P + lb + 2 * W];
+                    const T base = second_stage ? cur[c * P + li] : prev[c * P + li];
+                    const T dF = fr[c] - f[c];
+                    cur[c * P + li] = base - cx * dF;
                 }
-                face_flux<T, 2, V>(qa, qb, qc, qd, pbuf[lb - W], pbuf[lb], pbuf[lb + W], pbuf[lb + 2 * W], gamma,
-                                   f);
             }
-#pragma unroll
-            for (int c = 0; c < 4; ++c) fbuf[c * FS + i] = f[c];
         }
     }
     __syncthreads();
-    {  // C2: y update, then hand the finished cell to the store policy
-        for (int i = tid; i < cells; i += nthr) {
-            const int q = qdiv(i, inv_fw);
-            const int k = i - q * fw;
-            const int lx = x0 + k, ly = y0 + q;
-            const int li = ly * W + lx;
-            const int fi = q * fw + k;  // face j-1/2; face j+1/2 is fi + fw
-            T fl[4], out[4];
+    {  // Y: faces between rows y0-1+k and y0+k of column x0+c (k = 0..fh), the y update of cell (x0+c, y0+k), the store
+        const int nf = fh + 1, cnt = nf * fw;
+        const float inv = 1.0f / (float)nf;
+        for (int s = tid >> 6; 63 * s <= cnt - 2; s += slots) {
+            const int i = 63 * s + lane;
+            const int ic = i < cnt ? i : cnt - 1;
+            const int col = qdiv(ic, inv);
+            const int k = ic - col * nf;
+            const int a = y0 - 1 + k;
+            const int lx = x0 + col;
+            const int lb = a * PW + lx;
+            T g[4];
+            if (BC != 0 && a - 1 < ey && a + 2 >= ey) {
+                wall_face<T, 2, V, BC>(prev, pbuf, PW, P, lx, a, ey, a < ey, gamma, g);
+            } else {
+                T qa[4], qb[4], qc[4], qd[4];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) fl[c] = fbuf[c * FS + fi];
-            if (BC != 0 && ly == ey)  // the wall face as seen from this side
-                wall_face<T, 2, V, BC>(prev, pbuf, W, P, lx, ey - 1, ey, false, gamma, fl);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-                const T dG = fbuf[c * FS + fi + fw] - fl[c];
-                out[c] = cur[c * P + li] - cy * dG;
-                cur[c * P + li] = out[c];
+                for (int c = 0; c < 4; ++c) {
+                    qa[c] = prev[c * P + lb - PW];
+                    qb[c] = prev[c * P + lb];
+                    qc[c] = prev[c * P + lb + PW];
+                    qd[c] = prev[c * P + lb + 2 * PW];
+                }
+                face_flux<T, 2, V>(qa, qb, qc, qd, pbuf[lb - PW], pbuf[lb], pbuf[lb + PW], pbuf[lb + 2 * PW], gamma,
+                                   g);
             }
-            store(lx, ly, out);
+            T gr[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) gr[c] = next_lane(g[c]);
+            if (i < cnt && lane < 63 && k < fh) {
+                const int ly = a + 1;
+                const int li = lb + PW;
+                if (BC != 0 && ly == ey)  // the wall face as seen from this side
+                    wall_face<T, 2, V, BC>(prev, pbuf, PW, P, lx, ey - 1, ey, false, gamma, g);
+                T out[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const T dG = gr[c] - g[c];
+                    out[c] = cur[c * P + li] - cy * dG;
+                    cur[c * P + li] = out[c];
+                }
+                if constexpr (PNEXT) pcur[li] = pressure(out, gm1);
+                store(lx, ly, out);
+            }
         }
     }
 }
 
 // Swept store policy: cells outside F(l+2) go to the level's global buffer.
-template <typename T, int NVAR>
+// WRAP = false when the window stays inside the domain (no periodic wrap).
+template <typename T, int NVAR, bool WRAP = true>
 struct SweptStore {
     T* g;
     size_t NN;
@@ -366,7 +388,7 @@ struct SweptStore {
     {
         const int dx = lx - C, dy = ly - C;  // in F(l+2) <=> -hw2 <= d < hw2
         if ((dx >= -hx2) && (dx < hx2) && (dy >= -hy2) && (dy < hy2)) return;
-        const size_t gi = (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N);
+        const size_t gi = WRAP ? (size_t)wrapi(oy + ly, N) * N + wrapi(ox + lx, N) : (size_t)(oy + ly) * N + (ox + lx);
 #pragma unroll
         for (int c = 0; c < NVAR; ++c) g[c * NN + gi] = v[c];
     }
@@ -377,9 +399,12 @@ struct NoStore {
     __device__ __forceinline__ void operator()(int, int, const V*) const {}
 };
 
-// LDS layout of an Euler window: two level-parity state buffers (4 planes of
-// W*W), one pressure plane, one face buffer of 4 planes of FS values.
-__host__ __device__ inline size_t euler_lds_values(int W, int FS) { return (size_t)8 * W * W + W * W + 4 * FS; }
+// LDS layout of an Euler window of W x W cells with row pitch W + kEulerPad
+// (the pad staggers the banks of the column-wise face pass): two
+// level-parity state buffers of 4 planes, then the pressure planes of the two
+// level parities.
+constexpr int kEulerPad = 1;
+__host__ __device__ inline size_t euler_lds_values(int W) { return (size_t)10 * W * (W + kEulerPad); }
 
 // One heat level on the footprint [x0, x0+fw) x [y0, y0+fh) of the window.
 // Each thread takes two adjacent columns and walks a vertical strip of R
@@ -472,23 +497,28 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
     const int b = B > 0 ? B : a.tile, h = B > 0 ? B / (2 * R) : a.h, N = a.N, L = a.L;
     // heat pads its LDS rows by one value (fewer bank conflicts between the
     // rows a wave touches at once); Euler keeps the pitch W
-    const int W = b + 2 * R, PITCH = W + (NVAR == 1 ? kHeatPad : 0), P = PITCH * W;
+    const int W = b + 2 * R, PITCH = W + (NVAR == 1 ? kHeatPad : kEulerPad), P = PITCH * W;
     const size_t NN = (size_t)N * N;
     const int tiles = a.tiles, t2 = tiles * tiles;
 
-    // instance decode: phase 2w -> Octahedron (w, w); phase 2w-1 -> Bridges (w, w-1) then (w-1, w)
+    // instance decode: phase 2w -> Octahedron (w, w); phase 2w-1 -> Bridges (w, w-1) then (w-1, w);
+    // a heterogeneous advance launches only the tile rows jy < jrows (row-major order)
+    const int per = a.jrows > 0 ? tiles * a.jrows : t2;
     int wx, wy, inst = blk;
     if ((a.phase & 1) == 0) {
         wx = wy = a.phase >> 1;
     } else {
         const int w = (a.phase + 1) >> 1;
-        const int k = inst >= t2;
-        inst -= k * t2;
+        const int k = inst >= per;
+        inst -= k * per;
         wx = k ? w - 1 : w;
         wy = k ? w : w - 1;
     }
     int jx, jy;
-    if constexpr (ORDER_EDGE_FIRST) {
+    if (a.jrows > 0) {
+        jx = inst % tiles;
+        jy = inst / tiles;
+    } else if constexpr (ORDER_EDGE_FIRST) {
         // windows that cross the domain edge take the slower path (periodic
         // wrap or ghost values): give them the lowest workgroup indices so
         // they start first.  The wrapping row and column are jy = ey and
@@ -529,7 +559,13 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
     const RingSrc<T> src{reinterpret_cast<const T*>(a.buf0), reinterpret_cast<const T*>(a.buf1),
                          reinterpret_cast<const T*>(a.lvl0), TAPED ? reinterpret_cast<const T*>(a.q0) : nullptr,
                          TAPED ? reinterpret_cast<const T*>(a.q1) : nullptr, TAPED};
-    preload_rings<S, T>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C);
+    // global indices need the periodic wrap only when the window crosses the boundary
+    const bool wraps = ox < 0 || oy < 0 || ox + W > N || oy + W > N;
+    const T gm1 = (T)a.p[0] - T(1);  // Euler: gamma - 1 for the ring pressures (heat: unused)
+    if (wraps)
+        preload_rings<S, T, true>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
+    else
+        preload_rings<S, T, false>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
     __syncthreads();
 
     // level table of this shape type, indexed by the level within its window
@@ -542,8 +578,6 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         tab = a.tab + (wx > wy ? 2 * h : 3 * h);
         kbase = (wmax - 1) * h;
     }
-    // heat: global indices need the periodic wrap only when the window crosses the boundary
-    const bool wraps = ox < 0 || oy < 0 || ox + W > N || oy + W > N;
     for (int lvl = lo; lvl <= hi; ++lvl) {
         const LevelEntry e = tab[lvl - kbase];
         const bool has2 = lvl + 2 <= hi;
@@ -558,20 +592,24 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
             else
                 heat_level<T, false>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
         } else {
-            T* pbuf = lds + 2 * BUF;
-            T* fbuf = pbuf + P;
-            const int FS = (b + 1) * b;
+            const T* pprev = lds + 2 * BUF + ((lvl - 1) & 1) * P;
+            T* pcur = lds + 2 * BUF + (lvl & 1) * P;
             const bool second = (lvl & 1) == 0;
-            const SweptStore<T, NVAR> st{gout, NN, N, ox, oy, C, hx2, hy2};
-            if (S::BOUNDARY != 0 && wraps)
-                euler_level<T, S::SCHEME, SweptStore<T, NVAR>, S::BOUNDARY>(
-                    prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second, (T)a.p[0],
-                    (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]), st, window_edge(ox, W, N),
-                    window_edge(oy, W, N));
-            else
-                euler_level<T, S::SCHEME>(prev, cur, pbuf, fbuf, FS, W, P, e.x0, e.y0, e.fw, e.fh, second,
-                                          (T)a.p[0], (T)(second ? a.p[3] : a.p[1]), (T)(second ? a.p[4] : a.p[2]),
-                                          st);
+            const T g = (T)a.p[0], cxl = (T)(second ? a.p[3] : a.p[1]), cyl = (T)(second ? a.p[4] : a.p[2]);
+            if (wraps) {
+                const SweptStore<T, NVAR, true> st{gout, NN, N, ox, oy, C, hx2, hy2};
+                if (S::BOUNDARY != 0)
+                    euler_level<T, S::SCHEME, SweptStore<T, NVAR, true>, S::BOUNDARY>(
+                        prev, cur, pprev, pcur, PITCH, P, e.x0, e.y0, e.fw, e.fh, second, g, cxl, cyl, st,
+                        window_edge(ox, W, N), window_edge(oy, W, N));
+                else
+                    euler_level<T, S::SCHEME>(prev, cur, pprev, pcur, PITCH, P, e.x0, e.y0, e.fw, e.fh, second, g,
+                                              cxl, cyl, st);
+            } else {
+                const SweptStore<T, NVAR, false> st{gout, NN, N, ox, oy, C, hx2, hy2};
+                euler_level<T, S::SCHEME>(prev, cur, pprev, pcur, PITCH, P, e.x0, e.y0, e.fw, e.fh, second, g, cxl,
+                                          cyl, st);
+            }
         }
         __syncthreads();
     }

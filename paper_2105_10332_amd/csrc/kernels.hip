@@ -76,8 +76,10 @@ __global__ void __launch_bounds__(256) heat_standard_kernel(const T* __restrict_
 }
 
 // Euler: one full RK2 step per launch.  A TSxTS output tile loads Q^n on the
-// tile plus a 4-cell halo into LDS and runs the same level function as the
-// swept kernels twice: Q* on the tile plus 2 cells, then Q^{n+1} on the tile.
+// tile plus a 4-cell halo into LDS (row pitch W + kEulerPad) with the
+// pressure of every cell, and runs the same level function as the swept
+// kernels twice: Q* (and its pressures) on the tile plus 2 cells, then
+// Q^{n+1} on the tile.
 template <typename T>
 struct TileStore {
     T* out;
@@ -98,35 +100,40 @@ __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     const int TS = a.ts, N = a.N;
-    const int W = TS + 8, P = W * W, BUF = 4 * P, FS = (TS + 5) * (TS + 4);
+    const int W = TS + 8, PW = W + kEulerPad, P = PW * W, BUF = 4 * P;
     const size_t NN = (size_t)N * N;
     const int tx0 = blockIdx.x * TS, ty0 = blockIdx.y * TS;
-    const float inv_w = 1.0f / (float)W;
-    for (int i = threadIdx.x; i < P; i += blockDim.x) {
-        const int ly = qdiv(i, inv_w), lx = i - ly * W;
-        const size_t gi = (size_t)wrapi(ty0 - 4 + ly, N) * N + wrapi(tx0 - 4 + lx, N);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) lds[v * P + i] = in[v * NN + gi];
-    }
-    __syncthreads();
+    const T gamma = (T)a.p[0], gm1 = gamma - T(1);
     T* q0 = lds;
     T* q1 = lds + BUF;
-    T* pbuf = lds + 2 * BUF;
-    T* fbuf = pbuf + P;
-    const T gamma = (T)a.p[0];
+    T* p0 = lds + 2 * BUF;
+    T* p1 = p0 + P;
+    const float inv_w = 1.0f / (float)W;
+    for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
+        const int ly = qdiv(i, inv_w), lx = i - ly * W;
+        const size_t gi = (size_t)wrapi(ty0 - 4 + ly, N) * N + wrapi(tx0 - 4 + lx, N);
+        T s4[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) s4[v] = in[v * NN + gi];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) q0[v * P + ly * PW + lx] = s4[v];
+        p0[ly * PW + lx] = pressure(s4, gm1);
+    }
+    __syncthreads();
     const TileStore<T> st{out, NN, N, tx0 - 4, ty0 - 4};
     const int ex = window_edge(tx0 - 4, W, N), ey = window_edge(ty0 - 4, W, N);
     if (BC != 0 && (ex >= 0 || ey >= 0)) {  // a tile at the walls
-        euler_level<T, V, NoStore, BC>(q0, q1, pbuf, fbuf, FS, W, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1],
+        euler_level<T, V, NoStore, BC>(q0, q1, p0, p1, PW, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1],
                                        (T)a.p[2], NoStore{}, ex, ey);
         __syncthreads();
-        euler_level<T, V, TileStore<T>, BC>(q1, q0, pbuf, fbuf, FS, W, P, 4, 4, TS, TS, true, gamma, (T)a.p[3],
-                                            (T)a.p[4], st, ex, ey);
+        euler_level<T, V, TileStore<T>, BC, false>(q1, q0, p1, p0, PW, P, 4, 4, TS, TS, true, gamma, (T)a.p[3],
+                                                   (T)a.p[4], st, ex, ey);
     } else {
-        euler_level<T, V>(q0, q1, pbuf, fbuf, FS, W, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1], (T)a.p[2],
+        euler_level<T, V>(q0, q1, p0, p1, PW, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1], (T)a.p[2],
                           NoStore{});
         __syncthreads();
-        euler_level<T, V>(q1, q0, pbuf, fbuf, FS, W, P, 4, 4, TS, TS, true, gamma, (T)a.p[3], (T)a.p[4], st);
+        euler_level<T, V, TileStore<T>, 0, false>(q1, q0, p1, p0, PW, P, 4, 4, TS, TS, true, gamma, (T)a.p[3],
+                                                  (T)a.p[4], st);
     }
 }
 
@@ -270,8 +277,8 @@ static const void* phase_kernel(int kind, int dtype, int tile, int scheme, int b
 
 hipError_t launch_phase(int kind, int dtype, const PhaseArgs& a, int wg, size_t lds, hipStream_t st)
 {
-    const int t2 = a.tiles * a.tiles;
-    const int nblk = (a.phase & 1) ? 2 * t2 : t2;
+    const int per = a.tiles * (a.jrows > 0 ? a.jrows : a.tiles);
+    const int nblk = (a.phase & 1) ? 2 * per : per;
     void* args[] = {(void*)&a};
     return hipLaunchKernel(phase_kernel(kind, dtype, a.tile, a.scheme, a.bc, a.q0 != nullptr), dim3(nblk), dim3(wg),
                            args, lds, st);
@@ -315,13 +322,13 @@ hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, dou
 size_t euler_standard_lds(int dtype, int ts)
 {
     const size_t s = dtype == 0 ? 8 : 4;
-    return s * euler_lds_values(ts + 8, (ts + 5) * (ts + 4));
+    return s * euler_lds_values(ts + 8);
 }
 
 size_t euler_phase_lds(int dtype, int tile)
 {
     const size_t s = dtype == 0 ? 8 : 4;
-    return s * euler_lds_values(tile + 4, (tile + 1) * tile);
+    return s * euler_lds_values(tile + 4);
 }
 
 template <int V, int BC>

@@ -52,6 +52,7 @@ struct PhaseArgs {
     int tiles;    // N / b
     int L;        // final level of this advance
     int phase;    // 0 .. 2*ceil(L/h)
+    int jrows;    // heterogeneous advance: only the instances of tile rows jy < jrows (0: all)
     const LevelEntry* tab;  // level table (device memory, see above)
     double p[5];
 };

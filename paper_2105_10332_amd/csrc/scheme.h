@@ -1,7 +1,9 @@
 // scheme.h -- per-cell arithmetic of the two problems, shared by every
-// kernel (swept phases, Standard steps), so that Swept and Standard results
-// are bit-identical.  Device code only; compiled with -ffp-contract=off so
-// each expression is evaluated exactly as written (no fused multiply-add).
+// kernel (swept phases, Standard steps) and by the host cores' share of a
+// heterogeneous advance, so that all results are bit-identical.  Compiled
+// with -ffp-contract=off so each expression is evaluated exactly as written
+// (no fused multiply-add); divisions and square roots are correctly rounded
+// on both sides (IEEE on the host, the HIP expansions on the GPU).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -12,7 +14,7 @@ namespace swept {
 // Heat (App. A update equation), r = alpha dt / dx^2, dx = dy:
 // T' = (T + r*((T_{i+1} - 2T) + T_{i-1})) + r*((T_{j+1} - 2T) + T_{j-1}).
 template <typename T>
-__device__ __forceinline__ T heat_update(T c, T xp, T xm, T yp, T ym, T r)
+__host__ __device__ __forceinline__ T heat_update(T c, T xp, T xm, T yp, T ym, T r)
 {
     const T two_c = c + c;
     const T dxx = (xp - two_c) + xm;
@@ -24,7 +26,7 @@ __device__ __forceinline__ T heat_update(T c, T xp, T xm, T yp, T ym, T r)
 // State q = (rho, m = rho u, n = rho v, E).  Equation of state (App. B):
 // p = (gamma-1)(E - (m u + n v)/2).
 template <typename T>
-__device__ __forceinline__ T pressure(const T q[4], T gm1)
+__host__ __device__ __forceinline__ T pressure(const T q[4], T gm1)
 {
     const T u = q[1] / q[0];
     const T v = q[2] / q[0];
@@ -35,7 +37,7 @@ __device__ __forceinline__ T pressure(const T q[4], T gm1)
 // Physical flux along the axis whose momentum is q[A] (A = 1: F, A = 2: G,
 // App. B) and the signal speed |u_A| + c, c = sqrt(gamma p / rho).
 template <typename T, int A>
-__device__ __forceinline__ void phys_flux(const T q[4], T gamma, T gm1, T f[4], T& speed)
+__host__ __device__ __forceinline__ void phys_flux(const T q[4], T gamma, T gm1, T f[4], T& speed)
 {
     constexpr int Bc = (A == 1) ? 2 : 1;
     const T rho = q[0];
@@ -52,7 +54,7 @@ __device__ __forceinline__ void phys_flux(const T q[4], T gamma, T gm1, T f[4], 
 }
 
 template <typename T>
-__device__ __forceinline__ bool ratio_ok(T r)
+__host__ __device__ __forceinline__ bool ratio_ok(T r)
 {
     return r > T(0) && r < T(INFINITY);
 }
@@ -66,7 +68,7 @@ constexpr int kSpeedRoe = 2;        // spectral radius at the Roe-averaged state
 // axis A: sqrt(rho)-weighted velocities and total enthalpy H = (E + p)/rho,
 // c~^2 = (gamma - 1)(H~ - (u~^2 + v~^2)/2).
 template <typename T, int A>
-__device__ __forceinline__ T roe_speed(const T L[4], const T R[4], T gm1)
+__host__ __device__ __forceinline__ T roe_speed(const T L[4], const T R[4], T gm1)
 {
     constexpr int Bc = (A == 1) ? 2 : 1;
     const T wl = sqrt(L[0]), wr = sqrt(R[0]);
@@ -91,7 +93,7 @@ __device__ __forceinline__ T roe_speed(const T L[4], const T R[4], T gm1)
 // |u_R| + c_R); kLimiterLiteral swaps the factors to min(r_b, 1)/2 and
 // min(1/r_c, 1)/2; kSpeedRoe takes s at the Roe-averaged state.
 template <typename T, int A, int V = 0>
-__device__ __forceinline__ void face_flux(const T qa[4], const T qb[4], const T qc[4], const T qd[4], T pa, T pb,
+__host__ __device__ __forceinline__ void face_flux(const T qa[4], const T qb[4], const T qc[4], const T qd[4], T pa, T pb,
                                           T pc, T pd, T gamma, T out[4])
 {
     const T gm1 = gamma - T(1);

@@ -128,6 +128,39 @@ class SweptSolver:
             pass
 
 
+class SweptHetero:
+    """The GPU share of Eq. 2: a SweptSolver's advance split between the GPU (tile rows
+    below the share) and host worker threads (the rest), see swept.h.  The solver must
+    outlive this object."""
+
+    def __init__(self, solver: SweptSolver, gpu_share: float, cpu_threads: int = 0):
+        self.solver = solver
+        self._h = ctypes.c_void_p(0)
+        check(lib().swept_hetero_init(ctypes.byref(self._h), solver._ctx, float(gpu_share), int(cpu_threads)))
+
+    def swept_hetero_advance(self, n_steps: int):
+        check(lib().swept_set_stream(self.solver._ctx, _stream_ptr()))
+        check(lib().swept_hetero_advance(self._h, int(n_steps)))
+        return self.solver.state
+
+    def query(self):
+        """(GPU tile rows, host tile rows, host threads)."""
+        g, c, t = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        check(lib().swept_hetero_query(self._h, ctypes.byref(g), ctypes.byref(c), ctypes.byref(t)))
+        return g.value, c.value, t.value
+
+    def close(self):
+        if self._h:
+            lib().swept_hetero_destroy(self._h)
+            self._h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class SweptBatch:
     """Many problems (heat (N, N) and Euler (4, N, N) tensors, one dtype) advanced
     together by one persistent launch per swept_batch_advance (see swept.h).
@@ -243,6 +276,6 @@ def swept_cfl_dt_noalloc(state: torch.Tensor, length: float, cfl: float, gamma: 
     return out.value
 
 
-__all__ = ["SweptSolver", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_cfl_dt_noalloc", "swept_workspace_bytes", "make_problem", "HEAT",
+__all__ = ["SweptSolver", "SweptHetero", "SweptBatch", "SweptHeatAdvance", "swept_cfl_dt", "swept_cfl_dt_noalloc", "swept_workspace_bytes", "make_problem", "HEAT",
            "EULER", "LIMITER_LITERAL", "SPEED_ROE", "BC_PERIODIC", "BC_DIRICHLET", "BC_NEUMANN",
            "BC_REFLECT", "BATCH_COOPERATIVE", "BATCH_PER_PHASE", "_lib"]
