@@ -40,35 +40,67 @@ __global__ void __launch_bounds__((max_wg<S, T>())) swept_phase_kernel(PhaseArgs
 
 // ------------------------------------------------------------ Standard steps
 
-// Heat: one step per launch (Sec. 3.1 Standard).  Block 64 x 4 threads;
-// each thread walks STD_ROWS rows of one column, reusing the vertical
-// neighbours in registers.
-constexpr int STD_ROWS = 8;
+// Heat: one step per launch (Sec. 3.1 Standard).  A workgroup of STD_WG
+// threads covers STD_WG consecutive columns and STD_ROWS rows: each thread
+// walks the rows of its column, keeping the vertical neighbours in
+// registers, so the halo rows add 2/STD_ROWS to the reads.  The left and
+// right neighbours come from the adjacent lanes by DPP wavefront shifts; only
+// the lanes at a wavefront's edge (or next to a column past the grid) load
+// theirs, from cache lines the neighbouring wavefront of the same workgroup
+// reads anyway.
+constexpr int STD_ROWS = 16, STD_WG = 512;
+
+template <typename T>
+__device__ __forceinline__ T lane_shift(T v, bool next)
+{
+    if constexpr (sizeof(T) == 8) {
+        const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+        const int lo = (int)(unsigned)b, hi = (int)(unsigned)(b >> 32);
+        const unsigned l = next ? __builtin_amdgcn_update_dpp(0, lo, 0x130, 0xf, 0xf, false)
+                                : __builtin_amdgcn_update_dpp(0, lo, 0x138, 0xf, 0xf, false);
+        const unsigned h = next ? __builtin_amdgcn_update_dpp(0, hi, 0x130, 0xf, 0xf, false)
+                                : __builtin_amdgcn_update_dpp(0, hi, 0x138, 0xf, 0xf, false);
+        return __longlong_as_double((long long)(((unsigned long long)h << 32) | l));
+    } else {
+        const int i = __float_as_int(v);
+        return __int_as_float(next ? __builtin_amdgcn_update_dpp(0, i, 0x130, 0xf, 0xf, false)
+                                   : __builtin_amdgcn_update_dpp(0, i, 0x138, 0xf, 0xf, false));
+    }
+}
 
 // BC: 0 periodic; 1 Dirichlet (outside neighbours read bcv); 2 zero flux
 // (outside neighbours read the edge cell itself).
 template <typename T, int BC>
-__global__ void __launch_bounds__(256) heat_standard_kernel(const T* __restrict__ in, T* __restrict__ out, int N,
-                                                            T r, T bcv)
+__global__ void __launch_bounds__(STD_WG) heat_standard_kernel(const T* __restrict__ in, T* __restrict__ out, int N,
+                                                               T r, T bcv)
 {
-    const int x = blockIdx.x * 64 + threadIdx.x;
-    const int y0 = (blockIdx.y * 4 + threadIdx.y) * STD_ROWS;
-    if (x >= N || y0 >= N) return;
-    const int xm = wrapi(x - 1, N), xp = wrapi(x + 1, N);
-    T up = in[(size_t)wrapi(y0 - 1, N) * N + x];
-    T c = in[(size_t)y0 * N + x];
+    const int lane = threadIdx.x & 63;
+    const int x = blockIdx.x * STD_WG + threadIdx.x;
+    const int y0 = blockIdx.y * STD_ROWS;
+    const bool live = x < N;
+    const int xc = live ? x : N - 1;  // lanes past the grid read a valid column; they store nothing
+    const bool own_r = lane < 63 && x + 1 < N;  // lane + 1 holds column x + 1
+    const bool own_l = lane > 0;                // lane - 1 holds column x - 1
+    const int xm = wrapi(xc - 1, N), xp = wrapi(xc + 1, N);
+    T up = in[(size_t)wrapi(y0 - 1, N) * N + xc];
+    T c = in[(size_t)y0 * N + xc];
 #pragma unroll
     for (int k = 0; k < STD_ROWS; ++k) {
         const int y = y0 + k;
         if (y >= N) break;
-        const T dn = in[(size_t)wrapi(y + 1, N) * N + x];
         const size_t row = (size_t)y * N;
-        if constexpr (BC == 0) {
-            out[row + x] = heat_update<T>(c, in[row + xp], in[row + xm], dn, up, r);
-        } else {
-            const T g = BC == 1 ? bcv : c;
-            out[row + x] = heat_update<T>(c, x == N - 1 ? g : in[row + xp], x == 0 ? g : in[row + xm],
-                                          y == N - 1 ? g : dn, y == 0 ? g : up, r);
+        const T dn = in[(size_t)wrapi(y + 1, N) * N + xc];
+        T vr = lane_shift(c, true), vl = lane_shift(c, false);
+        if (!own_r) vr = in[row + xp];
+        if (!own_l) vl = in[row + xm];
+        if (live) {
+            if constexpr (BC == 0) {
+                out[row + x] = heat_update<T>(c, vr, vl, dn, up, r);
+            } else {
+                const T g = BC == 1 ? bcv : c;
+                out[row + x] = heat_update<T>(c, x == N - 1 ? g : vr, x == 0 ? g : vl, y == N - 1 ? g : dn,
+                                              y == 0 ? g : up, r);
+            }
         }
         up = c;
         c = dn;
@@ -300,7 +332,7 @@ hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds)
 template <typename T, int BC>
 static void heat_standard_launch(const void* in, void* out, int N, double r, double bcv, hipStream_t st)
 {
-    dim3 blk(64, 4), grd((N + 63) / 64, (N + 4 * STD_ROWS - 1) / (4 * STD_ROWS));
+    dim3 blk(STD_WG), grd((N + STD_WG - 1) / STD_WG, (N + STD_ROWS - 1) / STD_ROWS);
     hipLaunchKernelGGL((heat_standard_kernel<T, BC>), grd, blk, 0, st, (const T*)in, (T*)out, N, (T)r, (T)bcv);
 }
 
