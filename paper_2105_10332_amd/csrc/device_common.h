@@ -178,13 +178,17 @@ struct RingSrc {
 // Euler (NVAR = 4) also writes the pressure of every loaded value into the
 // pressure plane of its level parity (LDS after the two state buffers), so
 // that no level recomputes the pressures of its ring.
-template <class S, typename T, bool WRAP = true>
+template <class S, typename T, bool WRAP = true, int B = 0>
 __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>& src, int W, int P, int PITCH, int N,
                                               size_t NN,
                                               int ox, int oy, int wx, int wy, int lo, int hi, int h, int C,
                                               T gm1 = T(0))
 {
-    constexpr int NVAR = S::NVAR, KB = (NVAR * sizeof(T) >= 32) ? 2 : 4;
+    // heat with a compile-time tile B: enough cells per thread that a 512-thread workgroup loads
+    // its whole window in one batch (measured: 2% faster in FP32 than four cells per thread, the
+    // same in FP64)
+    constexpr int NVAR = S::NVAR;
+    constexpr int KB = NVAR == 4 ? ((NVAR * sizeof(T) >= 32) ? 2 : 4) : (B > 0 ? ((B + 2) * (B + 2) + 511) / 512 : 4);
     const T* __restrict__ g0 = src.g0;
     const T* __restrict__ g1 = src.g1;
     const T* __restrict__ z0 = src.lvl0;
@@ -434,8 +438,9 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
         const int x = e.x0 + 2 * (t - sidx * pw);
         const int ys = e.y0 + sidx * e.R;
         const int ye = min(ys + e.R, e.y0 + e.fh);
-        const bool xk0 = (x - C >= -hx2) && (x - C < hx2);
-        const bool xk1 = (x + 1 - C >= -hx2) && (x + 1 - C < hx2);
+        // the pair lies inside F(l+2) along x: both columns alike, since F(l+2) and the footprint
+        // have half-widths of equal parity (they differ by 0 or 2n = 2), so pairs never straddle it
+        const bool xk = (x - C >= -hx2) && (x - C < hx2);
         const int gx0 = WRAP ? wrapi(ox + x, N) : ox + x, gx1 = WRAP ? wrapi(ox + x + 1, N) : ox + x + 1;
         int gy = WRAP ? wrapi(oy + ys, N) : oy + ys;
         int grow = gy * N;
@@ -461,8 +466,10 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
             cur[li] = v0;
             cur[li + 1] = v1;
             const bool yk = (y >= ylo2) && (y < yhi2);
-            if (!(yk && xk0)) gout[grow + gx0] = v0;
-            if (!(yk && xk1)) gout[grow + gx1] = v1;
+            if (!(yk && xk)) {
+                gout[grow + gx0] = v0;
+                gout[grow + gx1] = v1;
+            }
             up0 = c0;
             up1 = c1;
             c0 = dn0;
@@ -563,9 +570,9 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
     const bool wraps = ox < 0 || oy < 0 || ox + W > N || oy + W > N;
     const T gm1 = (T)a.p[0] - T(1);  // Euler: gamma - 1 for the ring pressures (heat: unused)
     if (wraps)
-        preload_rings<S, T, true>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
+        preload_rings<S, T, true, B>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
     else
-        preload_rings<S, T, false>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
+        preload_rings<S, T, false, B>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
     __syncthreads();
 
     // level table of this shape type, indexed by the level within its window
