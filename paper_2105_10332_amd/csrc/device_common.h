@@ -481,6 +481,122 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
     }
 }
 
+// heat_level for a window inside the domain, with cheaper strip set-up: the
+// strip's position from 24-bit multiplies (full-rate; every operand is below
+// 2^23), and its global stores addressed by 32-bit byte offsets from gw, the
+// level buffer at the window's origin cell (ox, oy).  A window spans fewer than
+// 256 rows of at most 2^16 cells, so every offset fits in 32 bits.  The test
+// "inside F(l+2)" becomes one unsigned comparison per row.
+template <typename T>
+__device__ __forceinline__ void heat_level_inner(const T* __restrict__ prev, T* __restrict__ cur,
+                                                 char* __restrict__ gw, int W, int C, const LevelEntry& e, int hx2,
+                                                 int hy2, int N, T r)
+{
+    const int pw = e.pw, nthr = blockDim.x;
+    const unsigned rowb = (unsigned)N * (unsigned)sizeof(T);
+    const int yend = e.y0 + e.fh;
+    for (int t = threadIdx.x; t < pw * e.spc; t += nthr) {
+        const int sidx = qdiv(t, e.inv_pw);
+        const int x = e.x0 + 2 * (t - __mul24(sidx, pw));
+        const int ys = e.y0 + __mul24(sidx, e.R);
+        const int nr = min(e.R, yend - ys);
+        // rows y with (y - (C - hy2)) < span (unsigned) lie inside F(l+2) and are not stored;
+        // span = 0 when the pair is outside F(l+2) along x (see heat_level)
+        const bool xk = (unsigned)(x - C + hx2) < (unsigned)(2 * hx2);
+        const unsigned span = xk ? (unsigned)(2 * hy2) : 0u;
+        unsigned yrel = (unsigned)(ys - (C - hy2));
+        int li = __mul24(ys, W) + x;
+        unsigned boff = (unsigned)(__mul24(ys, N) + x) * (unsigned)sizeof(T);
+        T up0 = prev[li - W], up1 = prev[li - W + 1];
+        T c0 = prev[li], c1 = prev[li + 1];
+#pragma unroll 2
+        for (int k = 0; k < nr; ++k) {
+            const T dn0 = prev[li + W], dn1 = prev[li + W + 1];
+            const T lft = prev[li - 1], rgt = prev[li + 2];
+            const T v0 = heat_update<T>(c0, c1, lft, dn0, up0, r);
+            const T v1 = heat_update<T>(c1, rgt, c0, dn1, up1, r);
+            cur[li] = v0;
+            cur[li + 1] = v1;
+            if (yrel >= span) {
+                T* gp = reinterpret_cast<T*>(gw + boff);
+                gp[0] = v0;
+                gp[1] = v1;
+            }
+            up0 = c0;
+            up1 = c1;
+            c0 = dn0;
+            c1 = dn1;
+            li += W;
+            boff += rowb;
+            ++yrel;
+        }
+    }
+}
+
+// Up-front ring load of a heat window inside the domain (n = 1; not the
+// Up-Pyramid, and level 0 in buffer 0 when the window reaches it): the cells
+// and parities of ring_parities, in the same strided order as preload_rings,
+// with the strided cell index stepped in row/column form instead of divided
+// and the global reads addressed by 32-bit byte offsets from the window
+// origin in g0 and g1.  A cell at distance index a from the centre along the
+// growing axis (the larger of the two in an Octahedron, OCT) holds the
+// candidates t = a and t = a + 1, which lie at opposite level parities: the
+// one at parity p is t_p = a + ((base + a + 1 + p) % 2), loaded when
+// 1 <= t_p <= cap, cap = tcap (Octahedron) or min(tcap, h - s) (Bridge, s
+// the distance index along the shrinking axis, and at least 0).  Cells past the
+// window's last row have a >= h + 1 > cap (Octahedron, Y-Bridge) or cap = 0
+// (X-Bridge), so they need no separate test.
+template <typename T, int B, bool OCT>
+__device__ __forceinline__ void preload_heat_inner(T* lds, int BUF, const T* g0, const T* g1, int W, int PITCH,
+                                                   int N, int ox, int oy, bool xgrows, int base, int tcap, int h,
+                                                   int C)
+{
+    constexpr int KB = B > 0 ? ((B + 2) * (B + 2) + 511) / 512 : 4;
+    const int nthr = blockDim.x, tid = threadIdx.x;
+    const char* s0 = reinterpret_cast<const char*>(g0 + ((size_t)oy * N + ox));
+    const char* s1 = reinterpret_cast<const char*>(g1 + ((size_t)oy * N + ox));
+    const int sdy = nthr / W, sdx = nthr - sdy * W;  // the stride nthr in rows and columns
+    const int pb = (base + 1) & 1;
+    int ly = qdiv(tid, 1.0f / (float)W);
+    int lx = tid - ly * W;
+    for (int i0 = 0; i0 < W * W; i0 += KB * nthr) {
+        T v0[KB], v1[KB];
+        int li[KB];
+        bool n0[KB], n1[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            const int ax = lx >= C ? lx - C : C - 1 - lx;
+            const int ay = ly >= C ? ly - C : C - 1 - ly;
+            int a, cap;
+            if constexpr (OCT) {
+                a = max(ax, ay);
+                cap = tcap;
+            } else {
+                a = xgrows ? ax : ay;
+                cap = max(0, min(tcap, h - (xgrows ? ay : ax)));
+            }
+            const int pa = (a + pb) & 1;  // parity of t = a's level
+            n0[k] = (unsigned)(a + pa - 1) < (unsigned)cap;
+            n1[k] = (unsigned)(a - pa) < (unsigned)cap;
+            li[k] = __mul24(ly, PITCH) + lx;
+            const unsigned boff = (unsigned)(__mul24(ly, N) + lx) * (unsigned)sizeof(T);
+            if (n0[k]) v0[k] = *reinterpret_cast<const T*>(s0 + boff);
+            if (n1[k]) v1[k] = *reinterpret_cast<const T*>(s1 + boff);
+            lx += sdx;
+            ly += sdy;
+            if (lx >= W) {
+                lx -= W;
+                ++ly;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k) {
+            if (n0[k]) lds[li[k]] = v0[k];
+            if (n1[k]) lds[BUF + li[k]] = v1[k];
+        }
+    }
+}
+
 // Largest workgroup of a phase kernel (its launch bound).
 template <class S, typename T>
 constexpr int max_wg()
@@ -569,7 +685,19 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
     // global indices need the periodic wrap only when the window crosses the boundary
     const bool wraps = ox < 0 || oy < 0 || ox + W > N || oy + W > N;
     const T gm1 = (T)a.p[0] - T(1);  // Euler: gamma - 1 for the ring pressures (heat: unused)
-    if (wraps)
+    // heat windows inside the domain past the Up-Pyramid take the lean load (level 0 must then be
+    // buffer 0 itself whenever the window reaches it)
+    bool lean = false;
+    if constexpr (NVAR == 1 && !TAPED) lean = !wraps && wmax >= 1 && (wmax >= 2 || src.lvl0 == src.g0);
+    if (lean) {
+        const int base = (wmax - 1) * h;
+        if (wx == wy)
+            preload_heat_inner<T, B, true>(lds, BUF, src.g0, src.g1, W, PITCH, N, ox, oy, false, base,
+                                           min(h, hi - base), h, C);
+        else
+            preload_heat_inner<T, B, false>(lds, BUF, src.g0, src.g1, W, PITCH, N, ox, oy, wx > wy, base,
+                                            min(h - 1, hi - base), h, C);
+    } else if (wraps)
         preload_rings<S, T, true, B>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
     else
         preload_rings<S, T, false, B>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
@@ -597,7 +725,8 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
                 heat_level<T, true, S::BOUNDARY>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0],
                                                  (T)a.p[1]);
             else
-                heat_level<T, false>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0]);
+                heat_level_inner<T>(prev, cur, reinterpret_cast<char*>(gout + ((size_t)oy * N + ox)), PITCH, C, e,
+                                    hx2, hy2, N, (T)a.p[0]);
         } else {
             const T* pprev = lds + 2 * BUF + ((lvl - 1) & 1) * P;
             T* pcur = lds + 2 * BUF + (lvl & 1) * P;
