@@ -187,6 +187,9 @@ int half_width_host(int t, int h, int n)
 
 // Host copy of the per-level table (see launch.h).  t is the level within
 // the shape's window; Bridges' shrinking axis is at t + h.
+// Fewest rows per heat strip: a strip's set-up is paid once for all its rows.
+constexpr int kMinRows = 1;
+
 void build_level_table(const Derived& d, swept::LevelEntry* tab)
 {
     const int h = d.h, n = d.n, C = d.tile / 2 + n;
@@ -198,7 +201,7 @@ void build_level_table(const Derived& d, swept::LevelEntry* tab)
         e.fh = 2 * hy;
         e.pw = hx;  // fw is even: pairs of columns
         const int pairs = e.pw * e.fh;
-        e.R = pairs <= d.wg ? 1 : (pairs + d.wg - 1) / d.wg;
+        e.R = std::max((pairs + d.wg - 1) / d.wg, std::min(kMinRows, e.fh));
         e.spc = (e.fh + e.R - 1) / e.R;
         e.hx2 = hx2;
         e.hy2 = hy2;

@@ -492,25 +492,27 @@ __device__ __forceinline__ void heat_level_inner(const T* __restrict__ prev, T* 
                                                  char* __restrict__ gw, int W, int C, const LevelEntry& e, int hx2,
                                                  int hy2, int N, T r)
 {
-    const int pw = e.pw, nthr = blockDim.x;
+    const int pw = e.pw, R = e.R, nthr = blockDim.x, items = pw * e.spc;
     const unsigned rowb = (unsigned)N * (unsigned)sizeof(T);
-    const int yend = e.y0 + e.fh;
-    for (int t = threadIdx.x; t < pw * e.spc; t += nthr) {
+    const int yend = e.y0 + e.fh, ylo2 = C - hy2;
+    const unsigned span2 = (unsigned)(2 * hy2);
+    for (int t = threadIdx.x; t < items; t += nthr) {
         const int sidx = qdiv(t, e.inv_pw);
-        const int x = e.x0 + 2 * (t - __mul24(sidx, pw));
-        const int ys = e.y0 + __mul24(sidx, e.R);
-        const int nr = min(e.R, yend - ys);
+        const int x = e.x0 + 2 * (t - (int)__umul24(sidx, pw));
+        const int ys = e.y0 + (int)__umul24(sidx, R);
+        const int nr = min(R, yend - ys);  // at least 1: sidx < spc = ceil(fh / R)
+        __builtin_assume(nr >= 1);
         // rows y with (y - (C - hy2)) < span (unsigned) lie inside F(l+2) and are not stored;
         // span = 0 when the pair is outside F(l+2) along x (see heat_level)
-        const bool xk = (unsigned)(x - C + hx2) < (unsigned)(2 * hx2);
-        const unsigned span = xk ? (unsigned)(2 * hy2) : 0u;
-        unsigned yrel = (unsigned)(ys - (C - hy2));
-        int li = __mul24(ys, W) + x;
-        unsigned boff = (unsigned)(__mul24(ys, N) + x) * (unsigned)sizeof(T);
+        const unsigned span = (unsigned)(x - C + hx2) < (unsigned)(2 * hx2) ? span2 : 0u;
+        unsigned yrel = (unsigned)(ys - ylo2);
+        int li = (int)__umul24(ys, W) + x;
+        unsigned boff = ((unsigned)__umul24(ys, N) + (unsigned)x) * (unsigned)sizeof(T);
         T up0 = prev[li - W], up1 = prev[li - W + 1];
         T c0 = prev[li], c1 = prev[li + 1];
+        int k = 0;
 #pragma unroll 2
-        for (int k = 0; k < nr; ++k) {
+        do {
             const T dn0 = prev[li + W], dn1 = prev[li + W + 1];
             const T lft = prev[li - 1], rgt = prev[li + 2];
             const T v0 = heat_update<T>(c0, c1, lft, dn0, up0, r);
@@ -529,7 +531,7 @@ __device__ __forceinline__ void heat_level_inner(const T* __restrict__ prev, T* 
             li += W;
             boff += rowb;
             ++yrel;
-        }
+        } while (++k < nr);
     }
 }
 
