@@ -163,7 +163,8 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     const int W = b + 2, P = W * W;
     const size_t NN = (size_t)N * N;
     const int tiles = a.tiles, t2 = tiles * tiles;
-    const AdjLds lay = adjoint_lds_layout(sizeof(T), sizeof(L), b, pk_max, blockDim.x);
+    const int nthr = blockDim.x;
+    const AdjLds lay = adjoint_lds_layout(sizeof(T), sizeof(L), b, pk_max, nthr);
     T* tpar = reinterpret_cast<T*>(smem_raw);
     L* lpar = reinterpret_cast<L*>(smem_raw);  // the forward windows are dead once every level is packed
     T* pk = reinterpret_cast<T*>(smem_raw + lay.pk);
@@ -215,7 +216,7 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
         const RingSrc<T> src{reinterpret_cast<const T*>(a.buf0), reinterpret_cast<const T*>(a.buf1),
                              reinterpret_cast<const T*>(a.lvl0), reinterpret_cast<const T*>(a.q0),
                              reinterpret_cast<const T*>(a.q1), fx == 1 && fy == 1};
-        preload_rings<HeatS, T>(tpar, P, src, W, P, W, N, NN, ox, oy, fx, fy, flo, fhi, h, C);
+        preload_rings<HeatS, T>(tpar, P, src, W, P, W, N, NN, ox, oy, fx, fy, flo, fhi, h, C, nthr);
     }
     __syncthreads();
     const T bcv = (T)a.p[1];  // Dirichlet ghost value, rounded as the forward phases round it
@@ -236,7 +237,7 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     {
         const RingSrc<L> src{reinterpret_cast<const L*>(a.lam0), reinterpret_cast<const L*>(a.lam1),
                              reinterpret_cast<const L*>(a.lam0), nullptr, nullptr, false};
-        preload_rings<HeatS, L>(lpar, P, src, W, P, W, N, NN, ox, oy, kx, ky, klo, khi, h, C);
+        preload_rings<HeatS, L>(lpar, P, src, W, P, W, N, NN, ox, oy, kx, ky, klo, khi, h, C, nthr);
     }
     const LevelEntry* ktab;
     int kkbase;

@@ -182,7 +182,7 @@ template <class S, typename T, bool WRAP = true, int B = 0>
 __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>& src, int W, int P, int PITCH, int N,
                                               size_t NN,
                                               int ox, int oy, int wx, int wy, int lo, int hi, int h, int C,
-                                              T gm1 = T(0))
+                                              int nthr, T gm1 = T(0))
 {
     // heat with a compile-time tile B: enough cells per thread that a 512-thread workgroup loads
     // its whole window in one batch (measured: 2% faster in FP32 than four cells per thread, the
@@ -197,12 +197,12 @@ __device__ __forceinline__ void preload_rings(T* lds, int BUF, const RingSrc<T>&
     const bool owner_q = src.owner_q;
     const int cnt = W * W;
     const float invW = 1.0f / (float)W;
-    for (int base = 0; base < cnt; base += KB * (int)blockDim.x) {
+    for (int base = 0; base < cnt; base += KB * nthr) {
         T v[KB][2][NVAR];
         int li[KB], pm[KB];
 #pragma unroll
         for (int k = 0; k < KB; ++k) {
-            const int i = base + k * (int)blockDim.x + (int)threadIdx.x;
+            const int i = base + k * nthr + (int)threadIdx.x;
             pm[k] = 0;
             li[k] = i;
             if (i < cnt) {
@@ -286,10 +286,10 @@ __device__ __forceinline__ double next_lane(double v)
 template <typename T, int V, class Store, int BC = 0, bool PNEXT = true>
 __device__ __forceinline__ void euler_level(const T* __restrict__ prev, T* cur, const T* __restrict__ pbuf,
                                             T* __restrict__ pcur, int PW, int P, int x0, int y0, int fw, int fh,
-                                            bool second_stage, T gamma, T cx, T cy, const Store& store, int ex = 0,
-                                            int ey = 0)
+                                            bool second_stage, T gamma, T cx, T cy, const Store& store, int nthr,
+                                            int ex = 0, int ey = 0)
 {
-    const int nthr = blockDim.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const int lane = tid & 63, slots = nthr >> 6;
     const T gm1 = gamma - T(1);
     {  // X: faces between cells x0-1+k and x0+k of row y0+q (k = 0..fw), then the x update of cell x0+k
@@ -427,10 +427,10 @@ __host__ __device__ inline size_t euler_lds_values(int W) { return (size_t)10 * 
 template <typename T, bool WRAP, int BC = 0>
 __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __restrict__ cur, T* __restrict__ gout,
                                            int W, int C, const LevelEntry& e, int hx2, int hy2, int ox, int oy,
-                                           int N, T r, T bcv = T(0))
+                                           int N, T r, int nthr, T bcv = T(0))
 {
     static_assert(BC == 0 || WRAP, "boundaries are met only by windows that cross the edge");
-    const int pw = e.pw, nthr = blockDim.x;
+    const int pw = e.pw;
     const int NN = N * N;
     const int ylo2 = C - hy2, yhi2 = C + hy2;  // rows inside F(l+2)
     for (int t = threadIdx.x; t < pw * e.spc; t += nthr) {
@@ -490,9 +490,9 @@ __device__ __forceinline__ void heat_level(const T* __restrict__ prev, T* __rest
 template <typename T>
 __device__ __forceinline__ void heat_level_inner(const T* __restrict__ prev, T* __restrict__ cur,
                                                  char* __restrict__ gw, int W, int C, const LevelEntry& e, int hx2,
-                                                 int hy2, int N, T r)
+                                                 int hy2, int N, T r, int nthr)
 {
-    const int pw = e.pw, R = e.R, nthr = blockDim.x, items = pw * e.spc;
+    const int pw = e.pw, R = e.R, items = pw * e.spc;
     const unsigned rowb = (unsigned)N * (unsigned)sizeof(T);
     const int yend = e.y0 + e.fh, ylo2 = C - hy2;
     const unsigned span2 = (unsigned)(2 * hy2);
@@ -551,10 +551,10 @@ __device__ __forceinline__ void heat_level_inner(const T* __restrict__ prev, T* 
 template <typename T, int B, bool OCT>
 __device__ __forceinline__ void preload_heat_inner(T* lds, int BUF, const T* g0, const T* g1, int W, int PITCH,
                                                    int N, int ox, int oy, bool xgrows, int base, int tcap, int h,
-                                                   int C)
+                                                   int C, int nthr)
 {
     constexpr int KB = B > 0 ? ((B + 2) * (B + 2) + 511) / 512 : 4;
-    const int nthr = blockDim.x, tid = threadIdx.x;
+    const int tid = threadIdx.x;
     const char* s0 = reinterpret_cast<const char*>(g0 + ((size_t)oy * N + ox));
     const char* s1 = reinterpret_cast<const char*>(g1 + ((size_t)oy * N + ox));
     const int sdy = nthr / W, sdx = nthr - sdy * W;  // the stride nthr in rows and columns
@@ -597,6 +597,26 @@ __device__ __forceinline__ void preload_heat_inner(T* lds, int BUF, const T* g0,
             if (n1[k]) lds[BUF + li[k]] = v1[k];
         }
     }
+}
+
+// A level-table entry read through the constant address space (scalar loads),
+// field by field.
+typedef __attribute__((address_space(4))) LevelEntry ConstLevelEntry;
+__device__ __forceinline__ LevelEntry load_entry(const ConstLevelEntry* p)
+{
+    LevelEntry e;
+    e.x0 = p->x0;
+    e.y0 = p->y0;
+    e.fw = p->fw;
+    e.fh = p->fh;
+    e.hx2 = p->hx2;
+    e.hy2 = p->hy2;
+    e.pw = p->pw;
+    e.R = p->R;
+    e.spc = p->spc;
+    e.inv_fw = p->inv_fw;
+    e.inv_pw = p->inv_pw;
+    return e;
 }
 
 // Largest workgroup of a phase kernel (its launch bound).
@@ -687,6 +707,9 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
     // global indices need the periodic wrap only when the window crosses the boundary
     const bool wraps = ox < 0 || oy < 0 || ox + W > N || oy + W > N;
     const T gm1 = (T)a.p[0] - T(1);  // Euler: gamma - 1 for the ring pressures (heat: unused)
+    // the workgroup size, read once: a read inside a level would be a vector load whose wait
+    // also waits for the level's global stores
+    const int nthr = blockDim.x;
     // heat windows inside the domain past the Up-Pyramid take the lean load (level 0 must then be
     // buffer 0 itself whenever the window reaches it)
     bool lean = false;
@@ -695,14 +718,14 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         const int base = (wmax - 1) * h;
         if (wx == wy)
             preload_heat_inner<T, B, true>(lds, BUF, src.g0, src.g1, W, PITCH, N, ox, oy, false, base,
-                                           min(h, hi - base), h, C);
+                                           min(h, hi - base), h, C, nthr);
         else
             preload_heat_inner<T, B, false>(lds, BUF, src.g0, src.g1, W, PITCH, N, ox, oy, wx > wy, base,
-                                            min(h - 1, hi - base), h, C);
+                                            min(h - 1, hi - base), h, C, nthr);
     } else if (wraps)
-        preload_rings<S, T, true, B>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
+        preload_rings<S, T, true, B>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, nthr, gm1);
     else
-        preload_rings<S, T, false, B>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, gm1);
+        preload_rings<S, T, false, B>(lds, BUF, src, W, P, PITCH, N, NN, ox, oy, wx, wy, lo, hi, h, C, nthr, gm1);
     __syncthreads();
 
     // level table of this shape type, indexed by the level within its window
@@ -715,8 +738,12 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         tab = a.tab + (wx > wy ? 2 * h : 3 * h);
         kbase = (wmax - 1) * h;
     }
+    // the level table is read through the constant address space: nothing writes it during a
+    // launch, so every entry comes in with scalar loads, which a wait for the level's global
+    // stores never holds up (a vector load would share their counter)
+    const ConstLevelEntry* ctab = (const ConstLevelEntry*)(tab - kbase);
     for (int lvl = lo; lvl <= hi; ++lvl) {
-        const LevelEntry e = tab[lvl - kbase];
+        const LevelEntry e = load_entry(ctab + lvl);
         const bool has2 = lvl + 2 <= hi;
         const int hx2 = has2 ? e.hx2 : 0, hy2 = has2 ? e.hy2 : 0;
         const T* prev = lds + ((lvl - 1) & 1) * BUF;
@@ -725,10 +752,10 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
         if constexpr (NVAR == 1) {
             if (wraps)
                 heat_level<T, true, S::BOUNDARY>(prev, cur, gout, PITCH, C, e, hx2, hy2, ox, oy, N, (T)a.p[0],
-                                                 (T)a.p[1]);
+                                                 nthr, (T)a.p[1]);
             else
                 heat_level_inner<T>(prev, cur, reinterpret_cast<char*>(gout + ((size_t)oy * N + ox)), PITCH, C, e,
-                                    hx2, hy2, N, (T)a.p[0]);
+                                    hx2, hy2, N, (T)a.p[0], nthr);
         } else {
             const T* pprev = lds + 2 * BUF + ((lvl - 1) & 1) * P;
             T* pcur = lds + 2 * BUF + (lvl & 1) * P;
@@ -738,15 +765,15 @@ __device__ __forceinline__ void phase_instance(const PhaseArgs& a, int blk, unsi
                 const SweptStore<T, NVAR, true> st{gout, NN, N, ox, oy, C, hx2, hy2};
                 if (S::BOUNDARY != 0)
                     euler_level<T, S::SCHEME, SweptStore<T, NVAR, true>, S::BOUNDARY>(
-                        prev, cur, pprev, pcur, PITCH, P, e.x0, e.y0, e.fw, e.fh, second, g, cxl, cyl, st,
+                        prev, cur, pprev, pcur, PITCH, P, e.x0, e.y0, e.fw, e.fh, second, g, cxl, cyl, st, nthr,
                         window_edge(ox, W, N), window_edge(oy, W, N));
                 else
                     euler_level<T, S::SCHEME>(prev, cur, pprev, pcur, PITCH, P, e.x0, e.y0, e.fw, e.fh, second, g,
-                                              cxl, cyl, st);
+                                              cxl, cyl, st, nthr);
             } else {
                 const SweptStore<T, NVAR, false> st{gout, NN, N, ox, oy, C, hx2, hy2};
                 euler_level<T, S::SCHEME>(prev, cur, pprev, pcur, PITCH, P, e.x0, e.y0, e.fw, e.fh, second, g, cxl,
-                                          cyl, st);
+                                          cyl, st, nthr);
             }
         }
         __syncthreads();

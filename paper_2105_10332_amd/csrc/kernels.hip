@@ -141,7 +141,8 @@ __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict
     T* p0 = lds + 2 * BUF;
     T* p1 = p0 + P;
     const float inv_w = 1.0f / (float)W;
-    for (int i = threadIdx.x; i < W * W; i += blockDim.x) {
+    const int nthr = blockDim.x;
+    for (int i = threadIdx.x; i < W * W; i += nthr) {
         const int ly = qdiv(i, inv_w), lx = i - ly * W;
         const size_t gi = (size_t)wrapi(ty0 - 4 + ly, N) * N + wrapi(tx0 - 4 + lx, N);
         T s4[4];
@@ -156,16 +157,16 @@ __global__ void __launch_bounds__(256) euler_standard_kernel(const T* __restrict
     const int ex = window_edge(tx0 - 4, W, N), ey = window_edge(ty0 - 4, W, N);
     if (BC != 0 && (ex >= 0 || ey >= 0)) {  // a tile at the walls
         euler_level<T, V, NoStore, BC>(q0, q1, p0, p1, PW, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1],
-                                       (T)a.p[2], NoStore{}, ex, ey);
+                                       (T)a.p[2], NoStore{}, nthr, ex, ey);
         __syncthreads();
         euler_level<T, V, TileStore<T>, BC, false>(q1, q0, p1, p0, PW, P, 4, 4, TS, TS, true, gamma, (T)a.p[3],
-                                                   (T)a.p[4], st, ex, ey);
+                                                   (T)a.p[4], st, nthr, ex, ey);
     } else {
         euler_level<T, V>(q0, q1, p0, p1, PW, P, 2, 2, TS + 4, TS + 4, false, gamma, (T)a.p[1], (T)a.p[2],
-                          NoStore{});
+                          NoStore{}, nthr);
         __syncthreads();
         euler_level<T, V, TileStore<T>, 0, false>(q1, q0, p1, p0, PW, P, 4, 4, TS, TS, true, gamma, (T)a.p[3],
-                                                  (T)a.p[4], st);
+                                                  (T)a.p[4], st, nthr);
     }
 }
 
