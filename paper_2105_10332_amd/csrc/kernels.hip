@@ -40,15 +40,16 @@ __global__ void __launch_bounds__((max_wg<S, T>())) swept_phase_kernel(PhaseArgs
 
 // ------------------------------------------------------------ Standard steps
 
-// Heat: one step per launch (Sec. 3.1 Standard).  A workgroup of STD_WG
-// threads covers STD_WG consecutive columns and STD_ROWS rows: each thread
-// walks the rows of its column, keeping the vertical neighbours in
-// registers, so the halo rows add 2/STD_ROWS to the reads.  The left and
-// right neighbours come from the adjacent lanes by DPP wavefront shifts; only
-// the lanes at a wavefront's edge (or next to a column past the grid) load
-// theirs, from cache lines the neighbouring wavefront of the same workgroup
-// reads anyway.
-constexpr int STD_ROWS = 16, STD_WG = 512;
+// Heat: one step per launch (Sec. 3.1 Standard).  A workgroup of WG threads
+// covers WG consecutive columns and ROWS rows: each thread walks the rows of
+// its column, keeping the vertical neighbours in registers, so the halo rows
+// add 2/ROWS to the reads.  The left and right neighbours come from the
+// adjacent lanes by DPP wavefront shifts; only the lanes at a wavefront's
+// edge (or next to a column past the grid) load theirs, from cache lines the
+// neighbouring wavefront of the same workgroup reads anyway.  The launch takes
+// the largest of 512 x 16, 256 x 8 and 128 x 4 that still gives 2048
+// workgroups (measured per 500 FP64 steps: 4096^2 22.4 ms with 512 x 16,
+// 2048^2 6.5 ms with 256 x 8 against 7.6, 320^2 1.8 ms with 128 x 4 against 3.6).
 
 template <typename T>
 __device__ __forceinline__ T lane_shift(T v, bool next)
@@ -70,13 +71,13 @@ __device__ __forceinline__ T lane_shift(T v, bool next)
 
 // BC: 0 periodic; 1 Dirichlet (outside neighbours read bcv); 2 zero flux
 // (outside neighbours read the edge cell itself).
-template <typename T, int BC>
-__global__ void __launch_bounds__(STD_WG) heat_standard_kernel(const T* __restrict__ in, T* __restrict__ out, int N,
-                                                               T r, T bcv)
+template <typename T, int BC, int WG, int ROWS>
+__global__ void __launch_bounds__(WG) heat_standard_kernel(const T* __restrict__ in, T* __restrict__ out, int N, T r,
+                                                           T bcv)
 {
     const int lane = threadIdx.x & 63;
-    const int x = blockIdx.x * STD_WG + threadIdx.x;
-    const int y0 = blockIdx.y * STD_ROWS;
+    const int x = blockIdx.x * WG + threadIdx.x;
+    const int y0 = blockIdx.y * ROWS;
     const bool live = x < N;
     const int xc = live ? x : N - 1;  // lanes past the grid read a valid column; they store nothing
     const bool own_r = lane < 63 && x + 1 < N;  // lane + 1 holds column x + 1
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(STD_WG) heat_standard_kernel(const T* __restri
     T up = in[(size_t)wrapi(y0 - 1, N) * N + xc];
     T c = in[(size_t)y0 * N + xc];
 #pragma unroll
-    for (int k = 0; k < STD_ROWS; ++k) {
+    for (int k = 0; k < ROWS; ++k) {
         const int y = y0 + k;
         if (y >= N) break;
         const size_t row = (size_t)y * N;
@@ -333,8 +334,20 @@ hipError_t set_phase_lds_limit(int kind, int dtype, size_t lds)
 template <typename T, int BC>
 static void heat_standard_launch(const void* in, void* out, int N, double r, double bcv, hipStream_t st)
 {
-    dim3 blk(STD_WG), grd((N + STD_WG - 1) / STD_WG, (N + STD_ROWS - 1) / STD_ROWS);
-    hipLaunchKernelGGL((heat_standard_kernel<T, BC>), grd, blk, 0, st, (const T*)in, (T*)out, N, (T)r, (T)bcv);
+    const auto groups = [N](int wg, int rows) { return (long long)((N + wg - 1) / wg) * ((N + rows - 1) / rows); };
+    if (groups(512, 16) >= 2048) {
+        dim3 blk(512), grd((N + 511) / 512, (N + 15) / 16);
+        hipLaunchKernelGGL((heat_standard_kernel<T, BC, 512, 16>), grd, blk, 0, st, (const T*)in, (T*)out, N, (T)r,
+                           (T)bcv);
+    } else if (groups(256, 8) >= 2048) {
+        dim3 blk(256), grd((N + 255) / 256, (N + 7) / 8);
+        hipLaunchKernelGGL((heat_standard_kernel<T, BC, 256, 8>), grd, blk, 0, st, (const T*)in, (T*)out, N, (T)r,
+                           (T)bcv);
+    } else {
+        dim3 blk(128), grd((N + 127) / 128, (N + 3) / 4);
+        hipLaunchKernelGGL((heat_standard_kernel<T, BC, 128, 4>), grd, blk, 0, st, (const T*)in, (T*)out, N, (T)r,
+                           (T)bcv);
+    }
 }
 
 hipError_t launch_heat_standard(int dtype, const void* in, void* out, int N, double r, int bc, double bcv,
