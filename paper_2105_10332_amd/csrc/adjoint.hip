@@ -220,8 +220,11 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     }
     __syncthreads();
     const T bcv = (T)a.p[1];  // Dirichlet ghost value, rounded as the forward phases round it
+    // level entries through the constant address space: scalar loads, which no wait for the
+    // level's global stores holds up (see phase_instance)
+    const ConstLevelEntry* cftab = (const ConstLevelEntry*)(ftab - fkbase);
     for (int j = flo; j <= fhi; ++j) {
-        const LevelEntry e = ftab[j - fkbase];
+        const LevelEntry e = load_entry(cftab + j);
         if (BC != 0 && wraps)
             heat_level_pack<T, BC>(tpar + ((j - 1) & 1) * P, tpar + (j & 1) * P, pk + offs[j], W, e, r, ox, oy, N,
                                    bcv);
@@ -252,8 +255,9 @@ __global__ void __launch_bounds__(1024) adjoint_phase_kernel(PhaseArgs a, int pk
     L* l0 = reinterpret_cast<L*>(a.lam0);
     L* l1 = reinterpret_cast<L*>(a.lam1);
     double acc = 0.0;
+    const ConstLevelEntry* cktab = (const ConstLevelEntry*)(ktab - kkbase);
     for (int k = klo; k <= khi; ++k) {
-        const LevelEntry e = ktab[k - kkbase];
+        const LevelEntry e = load_entry(cktab + k);
         const bool has2 = k + 2 <= khi;
         const int hx2 = has2 ? e.hx2 : 0, hy2 = has2 ? e.hy2 : 0;
         const int j = h - k;

@@ -76,6 +76,7 @@ __device__ __forceinline__ void batch_phase(const PhaseArgs* __restrict__ probs,
             __syncthreads();
             it = *s_it;
         }
+        it = __builtin_amdgcn_readfirstlane(it);  // uniform: the instance's arguments come in as scalars
         if (it >= total) break;
         int lo = 0, hi = count;  // largest q with pre[q] <= it
         while (hi - lo > 1) {
@@ -83,7 +84,18 @@ __device__ __forceinline__ void batch_phase(const PhaseArgs* __restrict__ probs,
             if (pre[mid] <= it) lo = mid;
             else hi = mid;
         }
-        PhaseArgs a = probs[lo];
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        // the problem's arguments through the constant address space, word by word: scalar loads,
+        // so neither they nor the level table they point to wait behind the level's global stores
+        PhaseArgs a;
+        {
+            static_assert(sizeof(PhaseArgs) % 4 == 0, "copied in 32-bit words");
+            const __attribute__((address_space(4))) unsigned* src =
+                (const __attribute__((address_space(4))) unsigned*)(probs + lo);
+            unsigned* dst = reinterpret_cast<unsigned*>(&a);
+#pragma unroll
+            for (int w = 0; w < (int)(sizeof(PhaseArgs) / 4); ++w) dst[w] = src[w];
+        }
         a.phase = gp;
         a.L = (int)(n_steps * (a.kind == 0 ? 1 : 2));
         instance<T>(a, it - pre[lo], smem_raw);
