@@ -116,8 +116,7 @@ typedef struct {
 #define SWEPT_SPEED_ROE 2
 
 /* Launch tuning.  tile = block size b of Sec. 3.2 (0: library default);
- * wg = threads per workgroup (0: 256; a multiple of 64, at most 1024 for heat,
- * 512 for Euler FP32 and 256 for Euler FP64). */
+ * wg = threads per workgroup (0: 256; a multiple of 64, at most 1024). */
 typedef struct {
     int32_t tile;
     int32_t wg;

@@ -127,7 +127,7 @@ int derive(const swept_problem* p, const swept_tuning* t, Derived* d)
         return fail(SWEPT_ESHAPE, "tile %d needs %zu bytes of LDS (max %zu)", tile, d->lds_bytes, kLdsMax);
     int wg = t ? t->wg : 0;
     if (wg == 0) wg = 256;
-    const int wg_max = p->kind == SWEPT_HEAT ? 1024 : (p->dtype == SWEPT_F64 ? 256 : 512);
+    const int wg_max = 1024;
     if (wg < 64 || wg > wg_max || wg % 64 != 0)
         return fail(SWEPT_EINVAL, "wg=%d must be a multiple of 64 in [64,%d]", wg, wg_max);
     d->tile = tile;

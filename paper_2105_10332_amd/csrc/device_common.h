@@ -31,10 +31,10 @@ struct HeatSV {
 };
 using HeatS = HeatSV<0>;
 // Euler with scheme variant V (limiter and spectral-radius bits, scheme.h);
-// register-heavy per-cell update: at most 512 threads (FP32) or 256 (FP64)
+// up to 1024 threads (the per-cell update fits in 64 VGPRs in either precision)
 template <int V, int BC = 0>
 struct EulerSV {
-    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 512, SCHEME = V, BOUNDARY = BC;
+    static constexpr int NVAR = 4, R = 2, TWO_STAGE = 1, MAXWG = 1024, SCHEME = V, BOUNDARY = BC;
 };
 using EulerS = EulerSV<0>;
 
@@ -675,7 +675,7 @@ __device__ __forceinline__ LevelEntry load_entry(const ConstLevelEntry* p)
 template <class S, typename T>
 constexpr int max_wg()
 {
-    return (S::NVAR == 4 && sizeof(T) == 8) ? 256 : S::MAXWG;
+    return S::MAXWG;
 }
 
 // One shape instance (workgroup index blk) of phase a.phase; the body of the

@@ -69,7 +69,7 @@ def candidates(kind: str, dtype: str, n: int):
         except _lib.SweptError:
             continue
         tiles.append(b)
-    wgs = (64, 128, 256, 512, 1024) if kind == "heat" else ((128, 256) if dtype == "f64" else (128, 256, 512))
+    wgs = (64, 128, 256, 512, 1024) if kind == "heat" else (128, 256, 512, 1024)
     return [(b, wg) for b in tiles for wg in wgs]
 
 

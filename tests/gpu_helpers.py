@@ -28,9 +28,9 @@ def heat_gpu(T0: np.ndarray, r: float, steps: int, tile: int, method: str = "swe
 
 
 def euler_gpu(Q0: np.ndarray, dt: float, steps: int, tile: int, method: str = "swept", length: float = 10.0,
-              poison=False, scheme=0, bc=0):
+              poison=False, scheme=0, bc=0, wg=0):
     Q = torch.tensor(Q0, device=DEV)
-    s = SweptSolver(EULER, Q, dt=dt, length=length, gamma=1.4, tile=tile, scheme=scheme, boundary=bc)
+    s = SweptSolver(EULER, Q, dt=dt, length=length, gamma=1.4, tile=tile, scheme=scheme, boundary=bc, wg=wg)
     if poison:
         s.work[: s.info.state_bytes].fill_(255)
     getattr(s, method + "_advance")(steps)

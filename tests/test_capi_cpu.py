@@ -64,7 +64,7 @@ def test_workspace_size():
     (Problem(0, 5, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4), 16, 0, "SWEPT_EINVAL"),      # dtype
     (Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 0.9), 16, 0, "SWEPT_EINVAL"),    # gamma <= 1
     (heat(64), 16, 100, "SWEPT_EINVAL"),                                           # wg not multiple of 64
-    (euler(64), 16, 1024, "SWEPT_EINVAL"),                                         # Euler wg > 512
+    (euler(64), 16, 1088, "SWEPT_EINVAL"),                                         # wg > 1024
     (Problem(0, 0, 0, 0, 1.0, 1.0, 1e-5, 1.0, 1.4), 16, 0, "SWEPT_ESHAPE"),        # empty
     (Problem(1, 0, 64, 64, 10.0, 10.0, 1e-3, 0.0, 1.4, 4), 16, 0, "SWEPT_EINVAL"),  # unknown scheme bit
     (Problem(0, 0, 64, 64, 1.0, 1.0, 1e-5, 1.0, 1.4, 1), 16, 0, "SWEPT_EINVAL"),    # heat has no variants

@@ -34,6 +34,20 @@ def test_swept_equals_standard_and_oracle(dtype, tile, N):
         assert err <= (1e-10 if dtype == np.float64 else 1e-5), err
 
 
+@pytest.mark.parametrize("wg", [128, 512, 1024])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("tile,N", [(16, 48), (32, 96)])
+def test_workgroup_sizes(wg, dtype, tile, N):
+    """Every workgroup size up to the 1024-thread launch bound gives the Standard result."""
+    Q0 = problems.shu_vortex(N)
+    dt = _dt(Q0, N)
+    Q0 = Q0.astype(dtype)
+    steps = 2 * (tile // 4) + 3
+    sw = euler_gpu(Q0, dt, steps, tile, "swept", wg=wg)
+    st = euler_gpu(Q0, dt, steps, tile, "standard")
+    assert np.array_equal(sw, st), (wg, tile, N)
+
+
 @pytest.mark.parametrize("scheme", [1, 2, 3])
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("tile,N", [(8, 24), (16, 48), (32, 64)])
