@@ -43,17 +43,17 @@ METRIC = "cell-updates/s Swept vs Standard on 1 MI355X at equal accuracy; HBM GB
 # WRITE_SIZE x 1.0: the factors a plain copy of known size reads), keyed by workload and launch
 # shape, valid only for the kernel sources whose hash is recorded with it (null otherwise).
 MEASURED_TRAFFIC = {
-    ("heat", "f64", 4096, 64, 512, 1000): (639.3e6, "8cc44c2dd33bb177"),
-    ("heat", "f32", 4096, 64, 256, 1000): (371.1e6, "8cc44c2dd33bb177"),
-    ("euler", "f64", 2048, 16, 256, 500): (825.9e6, "8cc44c2dd33bb177"),
-    ("euler", "f32", 2048, 32, 512, 500): (478.5e6, "8cc44c2dd33bb177"),
+    ("heat", "f64", 4096, 64, 512, 1000): (632.4e6, "d2f8f8f34ab44653"),
+    ("heat", "f32", 4096, 64, 256, 1000): (371.0e6, "d2f8f8f34ab44653"),
+    ("euler", "f64", 2048, 32, 1024, 500): (694.5e6, "d2f8f8f34ab44653"),
+    ("euler", "f32", 2048, 32, 512, 500): (478.5e6, "d2f8f8f34ab44653"),
 }
 # The same two passes over the Standard kernels: HBM bytes per launch (one time step).
 MEASURED_STANDARD_TRAFFIC = {
-    ("heat", "f64", 4096): (293.8e6, "8cc44c2dd33bb177"),
-    ("heat", "f32", 4096): (151.0e6, "8cc44c2dd33bb177"),
-    ("euler", "f64", 2048): (538.6e6, "8cc44c2dd33bb177"),
-    ("euler", "f32", 2048): (336.8e6, "8cc44c2dd33bb177"),
+    ("heat", "f64", 4096): (293.7e6, "d2f8f8f34ab44653"),
+    ("heat", "f32", 4096): (151.0e6, "d2f8f8f34ab44653"),
+    ("euler", "f64", 2048): (538.6e6, "d2f8f8f34ab44653"),
+    ("euler", "f32", 2048): (336.8e6, "d2f8f8f34ab44653"),
 }
 KERNEL_SOURCES = ("scheme.h", "device_common.h", "kernels.hip", "launch.h")
 
@@ -569,7 +569,7 @@ def run_study(args):
                 except _lib.SweptError:
                     continue
                 best = None
-                for wg in ((64, 128, 256, 512, 1024) if kind == "heat" else (64, 128, 256)):
+                for wg in (64, 128, 256, 512, 1024):
                     st = x0.clone()
                     sv = SweptSolver(code, st, dt=dt, length=L, alpha=1.0, gamma=1.4, tile=b, wg=wg)
                     sv.swept_advance(M)
