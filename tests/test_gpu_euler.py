@@ -89,6 +89,23 @@ def test_walls_swept_equals_standard_and_oracle(bc, scheme, dtype, tile, N):
         assert err <= (1e-10 if dtype == np.float64 else 1e-5), (err, steps)
 
 
+@pytest.mark.parametrize("bc", [2, 3])
+@pytest.mark.parametrize("scheme", [0, 3])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_walls_with_1024_thread_workgroups(bc, scheme, dtype):
+    """The walled instantiations at the 1024-thread launch bound (tile 32, 96^2, 19 steps):
+    Swept == Standard bit for bit and both equal the walled oracle."""
+    N, tile, steps = 96, 32, 19
+    Q0 = problems.shu_vortex(N)
+    dt = _dt(Q0, N)
+    Q0 = Q0.astype(dtype)
+    sw = euler_gpu(Q0, dt, steps, tile, "swept", scheme=scheme, bc=bc, wg=1024)
+    st = euler_gpu(Q0, dt, steps, tile, "standard", scheme=scheme, bc=bc)
+    assert np.array_equal(sw, st), (bc, scheme)
+    ref = oracle.euler_run(Q0, dt, 10.0 / N, 10.0 / N, GAMMA, steps, scheme=scheme, bc=bc)
+    assert rel_err(sw, ref) <= (1e-10 if dtype == np.float64 else 1e-5)
+
+
 def test_slip_walls_conserve_mass_and_energy_on_gpu():
     """128^2 vortex against slip walls, 60 steps: the FP64 sums of rho and E stay constant
     to roundoff (a slip wall passes neither), the x momentum does not."""
