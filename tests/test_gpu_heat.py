@@ -119,6 +119,21 @@ def test_workgroup_sizes(wg):
     assert np.array_equal(a, st)
 
 
+@pytest.mark.parametrize("wg", [256, 512, 1024])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("tile", [16, 32, 64])
+def test_tiles_and_workgroups_equal_standard(tile, dtype, wg):
+    """Every fixed-tile heat instantiation at 256, 512 and 1024 threads on 4 x 4 tiles (windows
+    inside the domain and across its edge): runs that end inside the first window, after one
+    and over several cycles equal the Standard path bit for bit."""
+    n, h = 4 * tile, tile // 2
+    T0 = problems.heat_sine_noise(n, seed=tile + wg).astype(dtype)
+    for steps in sorted({1, h // 4, h // 4 + 1, h - 1, h + 1, 2 * h + 5, 4 * h + 3}):
+        sw, _ = heat_gpu(T0, 0.2, steps, tile, "swept", wg=wg)
+        st, _ = heat_gpu(T0, 0.2, steps, tile, "standard")
+        assert np.array_equal(sw, st), (tile, wg, steps)
+
+
 @pytest.mark.parametrize("dtype,tile", [(np.float64, 16), (np.float64, 32), (np.float64, 64), (np.float32, 32)])
 def test_c2_full_size_closed_form(dtype, tile):
     """4096^2, r = 0.2, 1000 steps, 16 Fourier modes: Swept equals Standard, and sampled
