@@ -9,7 +9,7 @@ import pytest
 import oracle
 from paper_2105_10332_amd import problems
 
-from gpu_helpers import heat_gpu, rel_err
+from gpu_helpers import DEV, heat_gpu, rel_err
 
 pytestmark = pytest.mark.gpu
 
@@ -117,6 +117,23 @@ def test_workgroup_sizes(wg):
     a, _ = heat_gpu(T0, 0.2, 41, 64, "swept", wg=wg)
     st, _ = heat_gpu(T0, 0.2, 41, 64, "standard")
     assert np.array_equal(a, st)
+
+
+@pytest.mark.parametrize("dtype_name", ["float64", "float32"])
+def test_state_not_16_byte_aligned_is_rejected(dtype_name):
+    """swept_init requires a 16-byte aligned state (and workspace): a state that starts one
+    value into its allocation is rejected with SWEPT_EINVAL, one at its start is taken."""
+    import torch
+
+    from paper_2105_10332_amd._lib import SweptError
+    from paper_2105_10332_amd.solver import HEAT, SweptSolver
+
+    n = 256
+    store = torch.zeros(n * n + 2, dtype=getattr(torch, dtype_name), device=DEV)
+    with pytest.raises(SweptError, match="16-byte aligned"):
+        SweptSolver(HEAT, store[1:1 + n * n].view(n, n), dt=0.2 / n / n, length=1.0, alpha=1.0, tile=64)
+    s = SweptSolver(HEAT, store[:n * n].view(n, n), dt=0.2 / n / n, length=1.0, alpha=1.0, tile=64)
+    s.close()
 
 
 @pytest.mark.parametrize("wg", [256, 512, 1024])
